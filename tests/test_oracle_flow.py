@@ -1,0 +1,99 @@
+"""Pins of the oracle's D2Q9 flow solver against what the mathematics fixes.
+
+The flow replaces the paper's 3D ESPResSo solve (Sec. "Lattice-Boltzmann for
+the Navier-Stokes equation") by a 2D D2Q9 BGK channel with a Zou-He parabolic
+velocity inlet and a Zou-He pressure outlet; these tests pin it against plane
+Poiseuille flow and against the mirror symmetry of the channel.
+"""
+import numpy as np
+import pytest
+
+from oracle import lbref as R
+from workloads import SOLID, channel, rasterize
+
+TAU = 0.8
+U0 = 0.05
+NU = (TAU - 0.5) / 3.0
+
+
+def _poiseuille(h, steps):
+    ny, nx = h + 2, 4 * h
+    t = channel(nx, ny)
+    f = R.flow_init(t, U0)
+    R.flow_run(t, f, TAU, U0, steps)
+    ux, uy, rho = R.flow_velocity(t, f, with_rho=True)
+    return t, ux, uy, rho
+
+
+@pytest.fixture(scope="module")
+def poiseuille():
+    return {16: _poiseuille(16, 20000), 32: _poiseuille(32, 40000)}
+
+
+def _shape_error(ux, ny, x):
+    """Max deviation of u_x(x, y) from the best-fitting parabola that vanishes
+    at the half-way walls y = 1/2 and y = ny - 3/2, relative to its maximum."""
+    y = np.arange(1, ny - 1)
+    par = (y - 0.5) * (ny - 1.5 - y)
+    prof = ux[1:-1, x]
+    a = (prof * par).sum() / (par * par).sum()
+    return np.abs(prof - a * par).max() / prof.max()
+
+
+def test_poiseuille_profile_second_order(poiseuille):
+    # plane Poiseuille flow is a parabola; the BGK half-way bounce-back wall
+    # error is second order in the channel width
+    e16 = _shape_error(poiseuille[16][1], 18, 32)
+    e32 = _shape_error(poiseuille[32][1], 34, 64)
+    assert e16 < 2e-3
+    assert e32 < 5e-4
+    assert 3.0 < e16 / e32 < 5.0
+
+
+def test_poiseuille_transverse_velocity_vanishes(poiseuille):
+    for h, (t, ux, uy, rho) in poiseuille.items():
+        ny, nx = t.shape
+        assert np.abs(uy[:, nx // 2]).max() < 1e-6 * U0
+
+
+def test_poiseuille_pressure_gradient(poiseuille):
+    # -dp/dx = 8 mu u_c / H^2 with p = rho/3 and mu = rho nu
+    ratios = []
+    for h, (t, ux, uy, rho) in poiseuille.items():
+        ny, nx = t.shape
+        xs = np.arange(nx // 4, 3 * nx // 4)
+        dpdx = np.polyfit(xs, rho[ny // 2, xs], 1)[0] / 3.0
+        xc = nx // 2
+        expect = -8.0 * NU * rho[ny // 2, xc] * ux[ny // 2, xc] / h ** 2
+        ratios.append(dpdx / expect)
+    assert all(abs(r - 1) < 0.02 for r in ratios)
+    assert abs(ratios[1] - 1) < abs(ratios[0] - 1)
+
+
+def test_outlet_density_is_one(poiseuille):
+    t, ux, uy, rho = poiseuille[16]
+    assert np.allclose(rho[1:-1, -1], 1.0, atol=1e-12)
+
+
+def test_mirror_symmetry_disc_on_centreline():
+    # a disc on the centre line of a symmetric channel: u_x even, u_y odd in y
+    nx, ny = 80, 41
+    t = channel(nx, ny)
+    rasterize(t, [(25, 20)], 5)
+    f = R.flow_init(t, U0)
+    R.flow_run(t, f, TAU, U0, 1500)
+    ux, uy = R.flow_velocity(t, f)
+    assert np.abs(ux - ux[::-1]).max() < 1e-14
+    assert np.abs(uy + uy[::-1]).max() < 1e-14
+    assert np.abs(uy).max() > 1e-4  # the disc does deflect the flow
+    assert (ux[t == SOLID] == 0).all()
+
+
+def test_mass_flux_constant_along_channel(poiseuille):
+    # steady state: the mass flux sum_y rho u_x is the same through every
+    # column of the upstream half of the channel (the pressure outlet's
+    # u_y = 0 closure leaves a layer that decays exponentially upstream)
+    for h, (t, ux, uy, rho) in poiseuille.items():
+        nx = t.shape[1]
+        j = (rho * ux)[1:-1, : nx // 2].sum(axis=0)
+        assert np.abs(j - j[0]).max() < 1e-6 * abs(j[0])
