@@ -1,0 +1,247 @@
+"""MI355X lattice-Boltzmann flow + advection-diffusion-reaction for catalytic
+fibre cross-sections (Sitaru & Gekle, arXiv 2109.04455).
+
+Thin Python binding of the C ABI in ``include/lbf.h``: the methods marshal
+arguments and device pointers; every step of the computation runs in the HIP
+kernels of ``liblbf.so``.  PyTorch provides the device memory (workspace,
+inputs, outputs) and the stream.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import LbfParams
+
+__all__ = ["LbfError", "LbfNotConverged", "Context", "params", "lib", "probe_copy",
+           "workspace_tensor"]
+
+
+class LbfError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+class LbfNotConverged(LbfError):
+    pass
+
+
+def lib():
+    return _lib.load()
+
+
+def _check(status, ctx_handle=None, what=""):
+    if status == _lib.OK:
+        return
+    L = lib()
+    msg = L.lbf_status_str(status).decode()
+    if ctx_handle is not None:
+        detail = L.lbf_last_error(ctx_handle)
+        if detail:
+            msg = f"{msg}: {detail.decode()}"
+    if what:
+        msg = f"{what}: {msg}"
+    cls = LbfNotConverged if status == _lib.ENOTCONV else LbfError
+    raise cls(status, msg)
+
+
+def params(nx, ny, *, real="f32", nspecies=3, tau_f=0.8, u0=0.05, tau_g=0.8, c_in=1.0,
+           vel_scale=1.0, flux_col=-1, tile_x=0, tile_y=0) -> LbfParams:
+    p = LbfParams()
+    _check(lib().lbf_params_default(ctypes.byref(p), nx, ny))
+    p.real_bytes = {"f32": 4, "f64": 8}[real]
+    p.nspecies = nspecies
+    p.tau_f, p.u0, p.tau_g, p.c_in, p.vel_scale = tau_f, u0, tau_g, c_in, vel_scale
+    p.flux_col, p.tile_x, p.tile_y = flux_col, tile_x, tile_y
+    return p
+
+
+def workspace_tensor(nbytes, device):
+    """A 256-byte aligned uint8 device tensor of at least nbytes."""
+    t = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+    off = (-t.data_ptr()) % 256
+    return t, t.data_ptr() + off
+
+
+def _stream_handle(stream):
+    return ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
+
+
+class Context:
+    """One lattice: geometry, flow, ADR species, observables, adjoint.
+
+    All device work is enqueued on ``stream`` (default: the current torch
+    stream when the context is created)."""
+
+    def __init__(self, p: LbfParams, device="cuda", stream=None):
+        self.p = p
+        self.device = torch.device(device)
+        self.real = {4: torch.float32, 8: torch.float64}[p.real_bytes]
+        self.nx, self.ny, self.ns = p.nx, p.ny, p.nspecies
+        h = ctypes.c_void_p()
+        st = lib().lbf_create(ctypes.byref(p), ctypes.byref(h))
+        self._h = h
+        if st != _lib.OK:
+            try:
+                _check(st, h, "lbf_create")
+            finally:
+                lib().lbf_destroy(h)
+                self._h = None
+        nbytes = ctypes.c_size_t()
+        _check(lib().lbf_workspace_bytes(h, ctypes.byref(nbytes)), h)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._ws, ptr = workspace_tensor(nbytes.value, self.device)
+        _check(lib().lbf_bind(h, ctypes.c_void_p(ptr), nbytes.value, _stream_handle(self.stream)), h,
+               "lbf_bind")
+        self._keep = []
+
+    # ---------------------------------------------------------------- helpers
+    def _call(self, name, *args):
+        _check(getattr(lib(), name)(self._h, *args), self._h, name)
+
+    def _dev(self, a, dtype):
+        t = torch.as_tensor(a)
+        return t.to(device=self.device, dtype=dtype).contiguous()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            torch.cuda.synchronize(self.device)
+            lib().lbf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --------------------------------------------------------------- set-up
+    def set_geometry(self, node_type):
+        t = self._dev(node_type, torch.uint8)
+        assert t.shape == (self.ny, self.nx)
+        with torch.cuda.stream(self.stream):
+            self._call("lbf_set_geometry", ctypes.c_void_p(t.data_ptr()))
+
+    def set_rates(self, k):
+        t = self._dev(k, torch.float64)
+        assert t.shape == (self.ny, self.nx)
+        with torch.cuda.stream(self.stream):
+            self._call("lbf_set_rates", ctypes.c_void_p(t.data_ptr()))
+
+    # ------------------------------------------------------------------ flow
+    def flow_init(self):
+        self._call("lbf_flow_init")
+
+    def flow_run(self, nsteps):
+        self._call("lbf_flow_run", int(nsteps))
+
+    def flow_steady(self, max_steps, check_every=1000, tol=1e-6, raise_not_converged=False):
+        steps = ctypes.c_long()
+        res = ctypes.c_double()
+        st = lib().lbf_flow_steady(self._h, int(max_steps), int(check_every), float(tol),
+                                   ctypes.byref(steps), ctypes.byref(res))
+        if st != _lib.ENOTCONV or raise_not_converged:
+            _check(st, self._h, "lbf_flow_steady")
+        return steps.value, res.value, st == _lib.OK
+
+    def get_velocity(self):
+        ux = torch.empty((self.ny, self.nx), dtype=self.real, device=self.device)
+        uy = torch.empty_like(ux)
+        self._call("lbf_get_velocity", ctypes.c_void_p(ux.data_ptr()), ctypes.c_void_p(uy.data_ptr()))
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return ux, uy
+
+    def set_velocity(self, ux, uy):
+        a = self._dev(ux, self.real)
+        b = self._dev(uy, self.real)
+        with torch.cuda.stream(self.stream):
+            self._call("lbf_set_velocity", ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()))
+        self._keep = [a, b]
+
+    # ------------------------------------------------------------------- ADR
+    def adr_init(self):
+        self._call("lbf_adr_init")
+
+    def adr_run(self, max_steps, check_every=1000, tol=0.0, raise_not_converged=False):
+        steps = ctypes.c_long()
+        st = lib().lbf_adr_run(self._h, int(max_steps), int(check_every), float(tol),
+                               ctypes.byref(steps))
+        if st != _lib.ENOTCONV or raise_not_converged:
+            _check(st, self._h, "lbf_adr_run")
+        return steps.value, st == _lib.OK
+
+    def efficiency(self):
+        eps = ctypes.c_double()
+        n = (ctypes.c_double * 3)()
+        inflow = ctypes.c_double()
+        self._call("lbf_efficiency", ctypes.byref(eps), n, ctypes.byref(inflow))
+        return eps.value, np.array(n[: self.ns]), inflow.value
+
+    def concentration(self, species):
+        out = torch.empty((self.ny, self.nx), dtype=self.real, device=self.device)
+        self._call("lbf_get_concentration", int(species), ctypes.c_void_p(out.data_ptr()))
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return out
+
+    def adr_steps(self):
+        s = ctypes.c_long()
+        self._call("lbf_adr_steps", ctypes.byref(s))
+        return s.value
+
+    # --------------------------------------------------------------- adjoint
+    def adjoint(self, T, ckpt_every=200, keep_trace=False):
+        """(eps, grad_k [ny, nx] float64 tensor) after T further steps."""
+        nbytes = ctypes.c_size_t()
+        self._call("lbf_adjoint_workspace_bytes", int(T), int(ckpt_every), int(bool(keep_trace)),
+                   ctypes.byref(nbytes))
+        ws, ptr = workspace_tensor(nbytes.value, self.device)
+        grad = torch.zeros((self.ny, self.nx), dtype=torch.float64, device=self.device)
+        eps = ctypes.c_double()
+        torch.cuda.synchronize(self.device)
+        self._call("lbf_adr_adjoint", int(T), int(ckpt_every), int(bool(keep_trace)),
+                   ctypes.c_void_p(ptr), nbytes.value, ctypes.byref(eps),
+                   ctypes.c_void_p(grad.data_ptr()))
+        del ws
+        return eps.value, grad
+
+    # ----------------------------------------------------- checkpoint/resume
+    def get_state(self):
+        n = ctypes.c_size_t()
+        self._call("lbf_state_bytes", ctypes.byref(n))
+        buf = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize(self.device)
+        self._call("lbf_get_state", ctypes.c_void_p(buf.data_ptr()))
+        return buf
+
+    def set_state(self, buf):
+        torch.cuda.synchronize(self.device)
+        self._call("lbf_set_state", ctypes.c_void_p(buf.data_ptr()))
+
+    # ---------------------------------------------------------------- timing
+    def time_adr_steps(self, nsteps):
+        ms = ctypes.c_double()
+        self._call("lbf_time_adr_steps", int(nsteps), ctypes.byref(ms))
+        return ms.value
+
+    def time_flow_steps(self, nsteps):
+        ms = ctypes.c_double()
+        self._call("lbf_time_flow_steps", int(nsteps), ctypes.byref(ms))
+        return ms.value
+
+
+def probe_copy(nbytes, device="cuda", stream=None):
+    """Time one device-to-device copy of nbytes with the library's copy kernel;
+    returns milliseconds."""
+    src = torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    s = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
+    torch.cuda.synchronize(device)
+    ms = ctypes.c_double()
+    _check(lib().lbf_probe_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                int(nbytes), _stream_handle(s), ctypes.byref(ms)))
+    return ms.value

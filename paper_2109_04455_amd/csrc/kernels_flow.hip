@@ -1,0 +1,224 @@
+// D2Q9 BGK flow kernels: one fused pull-stream / collide step per launch.
+//
+// Storage: populations after collision, shifted by their weights
+// (h_i = f_i - w_i, so that rho = 1 + sum h_i keeps FP32 precision), as a
+// structure of arrays [9][ny][nxp].  A step gathers h_i(x - c_i) (half-way
+// bounce-back at solid sources, Zou-He at the inlet x = 0 and outlet
+// x = nx-1), forms rho and u, relaxes to the second-order equilibrium with
+// omega = 1/tau_f and writes the result in place of the node's own slots of
+// the destination lattice.
+//
+// Paper: Sec. "Lattice-Boltzmann for the Navier-Stokes equation" (Eq. LBE;
+// bounce-back at the fibre surfaces).  The paper drives a periodic 3D box by
+// a body force; this 2D channel is driven by a parabolic velocity inlet
+// (Zou & He, 1997) instead.
+#include "stencil.hpp"
+
+namespace lbf {
+namespace {
+
+// D2Q9 velocities: rest, E, N, W, S, NE, NW, SW, SE
+constexpr int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+template <typename Real>
+__device__ __forceinline__ Real wgt(int i)
+{
+    return i == 0 ? Real(4) / Real(9) : (i < 5 ? Real(1) / Real(9) : Real(1) / Real(36));
+}
+
+template <typename Real>
+__device__ __forceinline__ Real inlet_u(int y, int ny, double u0)
+{
+    const double h = ny - 2.0;
+    return Real(4.0 * u0 * (y - 0.5) * (ny - 1.5 - y) / (h * h));
+}
+
+// Collide the shifted populations h in place; returns (u, v) and writes them.
+template <typename Real>
+__device__ __forceinline__ void collide(Real (&h)[9], Real omega, Real &u, Real &v)
+{
+    Real drho = 0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) drho += h[i];
+    const Real jx = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
+    const Real jy = (h[2] - h[4]) + (h[5] - h[8]) + (h[6] - h[7]);
+    const Real rho = Real(1) + drho;
+    const Real inv = Real(1) / rho;
+    u = jx * inv;
+    v = jy * inv;
+    const Real uu = Real(1.5) * (u * u + v * v);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const Real cu = Real(CX[i]) * u + Real(CY[i]) * v;
+        // f_eq - w = w (drho + rho (3 cu + 4.5 cu^2 - 1.5 u.u))
+        const Real heq = wgt<Real>(i) * (drho + rho * (Real(3) * cu + Real(4.5) * cu * cu - uu));
+        h[i] -= omega * (h[i] - heq);
+    }
+}
+
+template <typename Real, bool WRITE_U>
+__global__ __launch_bounds__(1024) void k_flow_step(FlowArgs<Real> a)
+{
+    int x, y;
+    tile_coords(a.L, x, y);
+    if (x >= a.nx || y >= a.ny) return;
+    const size_t id = (size_t)y * a.nxp + x;
+    const unsigned m = a.mask9[id];
+    if (m & MASK9_SOLID) return;
+    const size_t P = a.plane;
+    Real h[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int sx = x - CX[i];
+        if (sx < 0 || sx >= a.nx) {
+            h[i] = 0;  // open boundary: filled by Zou-He below
+        } else if (i != 0 && ((m >> (OPP[i] - 1)) & 1u)) {
+            h[i] = a.src[OPP[i] * P + id];  // half-way bounce-back
+        } else {
+            h[i] = a.src[i * P + id - CX[i] - (ptrdiff_t)CY[i] * a.nxp];
+        }
+    }
+    if (x == 0) {
+        // Zou-He velocity inlet, u = (u_in(y), 0): unknown E, NE, SE.
+        // In shifted form the known sum f0+fN+fS+2(fW+fNW+fSW) is 1 + sum h.
+        const Real ux = inlet_u<Real>(y, a.ny, a.u0);
+        const Real rho = (Real(1) + h[0] + h[2] + h[4] + Real(2) * (h[3] + h[6] + h[7])) / (Real(1) - ux);
+        h[1] = h[3] + Real(2) / Real(3) * rho * ux;
+        h[5] = h[7] - Real(0.5) * (h[2] - h[4]) + rho * ux / Real(6);
+        h[8] = h[6] + Real(0.5) * (h[2] - h[4]) + rho * ux / Real(6);
+    } else if (x == a.nx - 1) {
+        // Zou-He pressure outlet, rho = 1, u_y = 0: unknown W, NW, SW
+        const Real ux = h[0] + h[2] + h[4] + Real(2) * (h[1] + h[5] + h[8]);
+        h[3] = h[1] - Real(2) / Real(3) * ux;
+        h[6] = h[8] - Real(0.5) * (h[2] - h[4]) - ux / Real(6);
+        h[7] = h[5] + Real(0.5) * (h[2] - h[4]) - ux / Real(6);
+    }
+    Real u, v;
+    collide(h, a.omega, u, v);
+    if (WRITE_U) {
+        a.u[id] = u;
+        a.u[P + id] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) a.dst[i * P + id] = h[i];
+}
+
+// Initial state f = f_eq(1, (u_in(y), 0)), then one collision (the stored
+// state is always post-collision).
+template <typename Real>
+__global__ __launch_bounds__(1024) void k_flow_init(FlowArgs<Real> a)
+{
+    int x, y;
+    tile_coords(a.L, x, y);
+    if (x >= a.nx || y >= a.ny) return;
+    const size_t id = (size_t)y * a.nxp + x;
+    const size_t P = a.plane;
+    const unsigned m = a.mask9[id];
+    if (m & MASK9_SOLID) {
+        a.u[id] = 0;
+        a.u[P + id] = 0;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) a.dst[i * P + id] = 0;
+        return;
+    }
+    const Real ux = inlet_u<Real>(y, a.ny, a.u0);
+    Real h[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const Real cu = Real(CX[i]) * ux;
+        h[i] = wgt<Real>(i) * (Real(3) * cu + Real(4.5) * cu * cu - Real(1.5) * ux * ux);
+    }
+    Real u, v;
+    collide(h, a.omega, u, v);
+    a.u[id] = u;
+    a.u[P + id] = v;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) a.dst[i * P + id] = h[i];
+}
+
+// max |u - u_prev| over fluid nodes (both components); copies u -> u_prev.
+// Non-finite velocities give +inf.  Per-block maxima, then one block.
+template <typename Real>
+__global__ __launch_bounds__(256) void k_du_max(const Real *u, Real *uprev, const uint16_t *mask9,
+                                                size_t plane, double *partial)
+{
+    __shared__ double sm[256];
+    double mx = 0.0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * plane;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const size_t id = i < plane ? i : i - plane;
+        if (mask9[id] & MASK9_SOLID) continue;
+        const double a = (double)u[i], b = (double)uprev[i];
+        double d = fabs(a - b);
+        if (!isfinite(a)) d = INFINITY;
+        mx = fmax(mx, d);
+        uprev[i] = u[i];
+    }
+    sm[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sm[0];
+}
+
+__global__ __launch_bounds__(256) void k_max_partials(const double *partial, int n, double *out)
+{
+    __shared__ double sm[256];
+    double mx = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) mx = fmax(mx, partial[i]);
+    sm[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sm[0];
+}
+
+}  // namespace
+
+hipError_t launch_flow_init(int real_bytes, const FlowArgs<float> &af, const FlowArgs<double> &ad,
+                            hipStream_t s)
+{
+    if (real_bytes == 4)
+        hipLaunchKernelGGL(k_flow_init<float>, af.L.grid(), af.L.block(), 0, s, af);
+    else
+        hipLaunchKernelGGL(k_flow_init<double>, ad.L.grid(), ad.L.block(), 0, s, ad);
+    return hipGetLastError();
+}
+
+hipError_t launch_flow_step(int real_bytes, bool write_u, const FlowArgs<float> &af,
+                            const FlowArgs<double> &ad, hipStream_t s)
+{
+    if (real_bytes == 4) {
+        if (write_u)
+            hipLaunchKernelGGL((k_flow_step<float, true>), af.L.grid(), af.L.block(), 0, s, af);
+        else
+            hipLaunchKernelGGL((k_flow_step<float, false>), af.L.grid(), af.L.block(), 0, s, af);
+    } else {
+        if (write_u)
+            hipLaunchKernelGGL((k_flow_step<double, true>), ad.L.grid(), ad.L.block(), 0, s, ad);
+        else
+            hipLaunchKernelGGL((k_flow_step<double, false>), ad.L.grid(), ad.L.block(), 0, s, ad);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_du_max(int real_bytes, const void *u, void *uprev, const uint16_t *mask9,
+                         size_t plane, double *partial, int nblocks, double *out, hipStream_t s)
+{
+    if (real_bytes == 4)
+        hipLaunchKernelGGL(k_du_max<float>, dim3(nblocks), dim3(256), 0, s, (const float *)u,
+                           (float *)uprev, mask9, plane, partial);
+    else
+        hipLaunchKernelGGL(k_du_max<double>, dim3(nblocks), dim3(256), 0, s, (const double *)u,
+                           (double *)uprev, mask9, plane, partial);
+    hipLaunchKernelGGL(k_max_partials, dim3(1), dim3(256), 0, s, partial, nblocks, out);
+    return hipGetLastError();
+}
+
+}  // namespace lbf

@@ -1,0 +1,221 @@
+"""GPU path vs the FP64 oracle, element by element on the same seeded inputs.
+
+Parity bars: FP64 kernels within 1e-10 (relative, fields and eps); FP32
+kernels within 1e-4 relative on eps and on the concentration fields (field
+metric: max |C_gpu - C_ref| / max |C_ref| per species), velocities within
+1e-4 u0.  All comparisons are at identical step counts.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import lbref as R
+from workloads import make_workload
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _gpu():
+    import paper_2109_04455_amd as L
+    return L
+
+
+def _ctx(w, real=None, **kw):
+    L = _gpu()
+    real = real or w.real
+    p = L.params(w.nx, w.ny, real=real, nspecies=w.nspecies, tau_f=w.tau_f, u0=w.u0,
+                 tau_g=w.tau_g, c_in=w.c_in, vel_scale=w.vel_scale, **kw)
+    c = L.Context(p)
+    c.set_geometry(w.node_type)
+    c.set_rates(w.k)
+    return c
+
+
+def _field_err(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _oracle(w, flow_steps, adr_steps):
+    ux, uy, _, _ = R.flow_steady(w.node_type, w.tau_f, w.u0, flow_steps, tol=0)
+    g = R.adr_init(w.node_type, ux, uy, w.nspecies, w.c_in, w.vel_scale)
+    R.adr_run(w.node_type, w.k, ux, uy, g, w.tau_g, adr_steps, w.c_in, w.vel_scale)
+    flux, inflow = R.adr_observe(w.node_type, g, w.c_in)
+    return {"ux": ux, "uy": uy, "c": R.adr_concentration(w.node_type, g), "N": flux,
+            "inflow": inflow, "eps": R.efficiency(flux)}
+
+
+def _gpu_run(w, flow_steps, adr_steps, real=None, **kw):
+    c = _ctx(w, real, **kw)
+    c.flow_init()
+    c.flow_run(flow_steps)
+    ux, uy = c.get_velocity()
+    c.adr_init()
+    c.adr_run(adr_steps, check_every=1000, tol=0)
+    eps, N, inflow = c.efficiency()
+    conc = np.stack([c.concentration(s).double().cpu().numpy() for s in range(w.nspecies)])
+    return {"ux": ux.double().cpu().numpy(), "uy": uy.double().cpu().numpy(), "c": conc, "N": N,
+            "inflow": inflow, "eps": eps, "ctx": c}
+
+
+def _compare(g, o, w, tol_u, tol_c, tol_n):
+    du = max(np.abs(g["ux"] - o["ux"]).max(), np.abs(g["uy"] - o["uy"]).max()) / w.u0
+    assert du <= tol_u, f"velocity error {du:.3e}"
+    for s in range(w.nspecies):
+        e = _field_err(g["c"][s], o["c"][s])
+        assert e <= tol_c, f"species {s} field error {e:.3e}"
+    dn = np.abs(np.asarray(g["N"]) - o["N"]).max() / abs(o["inflow"])
+    assert dn <= tol_n, f"flux error {dn:.3e}"
+    assert abs(g["inflow"] - o["inflow"]) <= tol_n * abs(o["inflow"])
+
+
+# ------------------------------------------------------------------ C0, FP64
+@pytest.fixture(scope="module")
+def c0_oracle():
+    w = make_workload("C0")
+    return w, _oracle(w, 10000, 2000)
+
+
+def test_c0_fp64_flow_and_adr_parity(c0_oracle):
+    w, o = c0_oracle
+    g = _gpu_run(w, 10000, 2000, real="f64")
+    _compare(g, o, w, 1e-10, 1e-10, 1e-10)
+    assert abs(g["eps"] / o["eps"] - 1) < 1e-9
+
+
+def test_c0_fp32_flow_and_adr_parity(c0_oracle):
+    w, o = c0_oracle
+    g = _gpu_run(w, 10000, 2000, real="f32")
+    _compare(g, o, w, 1e-4, 1e-4, 1e-5)
+    assert abs(g["eps"] / o["eps"] - 1) < 1e-3  # eps is still tiny at 2000 steps
+
+
+def test_c0_end_to_end_matches_oracle_convergence():
+    # the oracle's converged run (tests/golden/make_golden.py)
+    ref = json.load(open(os.path.join(HERE, "golden", "c0_oracle.json")))
+    w = make_workload("C0")
+    c = _ctx(w, "f64")
+    c.flow_init()
+    steps_f, res, _ = c.flow_steady(ref["flow_steps"], 1000, tol=0)
+    assert steps_f == ref["flow_steps"]
+    c.adr_init()
+    steps, conv = c.adr_run(400000, check_every=ref["check_every"], tol=ref["tol"])
+    assert conv and steps == ref["adr_steps"]
+    eps, N, inflow = c.efficiency()
+    assert abs(eps / ref["eps"] - 1) < 1e-9
+    assert np.abs(N - np.array(ref["N"])).max() < 1e-9 * ref["inflow"]
+    # at steady state everything that flows in leaves as A or B
+    assert abs(N.sum() - inflow) < 1e-6 * inflow
+
+
+# --------------------------------------------------------- tiny cascade case
+@pytest.mark.parametrize("real,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_tiny_cascade_parity_converged(real, tol):
+    w = make_workload("tiny")
+    o = _oracle(w, 3000, 12000)
+    g = _gpu_run(w, 3000, 12000, real=real)
+    _compare(g, o, w, tol, tol, tol)
+    assert abs(g["eps"] / o["eps"] - 1) < tol
+    # steady cascade: N_A + N_B + N_C = inflow of A
+    assert abs(sum(g["N"]) - g["inflow"]) < 10 * tol * g["inflow"]
+
+
+# --------------------------------------------- scaled and full-size FP32
+def test_c1_quarter_fp32_parity():
+    w = make_workload("C1q")
+    o = _oracle(w, 2000, 3000)
+    g = _gpu_run(w, 2000, 3000)
+    _compare(g, o, w, 1e-4, 1e-4, 1e-5)
+
+
+def test_c2_quarter_fp32_parity_ragged_tiles():
+    # 1024 x 256 with a tile shape that leaves ragged edges (ny % 3 != 0)
+    w = make_workload("C2q")
+    o = _oracle(w, 500, 1500)
+    g = _gpu_run(w, 500, 1500, tile_x=64, tile_y=3)
+    _compare(g, o, w, 1e-4, 1e-4, 1e-5)
+
+
+@pytest.mark.parametrize("name", ["C1", "C2"])
+def test_full_size_short_run_parity(name):
+    # full-size lattices in the default launch configuration, short runs
+    w = make_workload(name)
+    o = _oracle(w, 30, 30)
+    g = _gpu_run(w, 30, 30)
+    _compare(g, o, w, 1e-4, 1e-4, 1e-5)
+
+
+def test_odd_width_fp64_parity():
+    # nx not a multiple of the 64-wide row padding, both precisions' edge paths
+    from workloads import channel, rasterize, CAT1, CAT2
+    from workloads.geometry import classify_surface
+    nx, ny = 75, 23
+    t = channel(nx, ny)
+    own = rasterize(t, [(20, 11), (45, 12)], 3)
+    surf = classify_surface(t, own)
+    t[surf & (own == 0)] = CAT1
+    t[surf & (own == 1)] = CAT2
+    k = np.where(t >= CAT1, 0.2, 0.0)
+    from workloads.configs import Workload, lattice_params
+    w = Workload("odd", t, k, 3, lattice_params(3.0, 5.0, 3), real="f64")
+    o = _oracle(w, 800, 1500)
+    g = _gpu_run(w, 800, 1500)
+    _compare(g, o, w, 1e-10, 1e-10, 1e-10)
+
+
+# --------------------------------------------------- execution-path checks
+def test_graph_replay_equals_direct_launches():
+    w = make_workload("tiny", real="f32")
+    a = _ctx(w)
+    b = _ctx(w)
+    for c in (a, b):
+        c.flow_init()
+        c.flow_run(500)
+        c.adr_init()
+    a.adr_run(1000, check_every=1000, tol=0)   # one captured graph of 1000 steps
+    b.adr_run(1000, check_every=5, tol=0)      # blocks below the graph threshold
+    for s in range(3):
+        assert torch.equal(a.concentration(s), b.concentration(s))
+    assert a.efficiency()[0] == b.efficiency()[0]
+
+
+def test_state_roundtrip_is_bit_exact():
+    w = make_workload("tiny", real="f32")
+    c = _ctx(w)
+    c.flow_init()
+    c.flow_run(500)
+    c.adr_init()
+    c.adr_run(300, tol=0)
+    st = c.get_state()
+    c.adr_run(700, tol=0)
+    e1 = c.efficiency()[0]
+    c1 = c.concentration(2).clone()
+    c.set_state(st)
+    assert c.adr_steps() == 300
+    c.adr_run(700, tol=0)
+    assert c.efficiency()[0] == e1
+    assert torch.equal(c.concentration(2), c1)
+
+
+def test_error_paths_on_device():
+    L = _gpu()
+    w = make_workload("tiny")
+    c = _ctx(w)
+    with pytest.raises(L.LbfError) as e:
+        c.efficiency()
+    assert e.value.status == -6
+    with pytest.raises(L.LbfError):
+        c.adr_run(10)                       # no adr_init yet
+    bad = w.k.copy()
+    bad[w.node_type >= 2] = 1.5
+    with pytest.raises(L.LbfError) as e:
+        c.set_rates(bad)
+    assert e.value.status == -1
+    t = w.node_type.copy()
+    t[0, 5] = 0
+    with pytest.raises(L.LbfError):
+        c.set_geometry(t)                   # wall row must be solid
