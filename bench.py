@@ -1,0 +1,183 @@
+"""Benchmark: forward LB-ADR throughput (MLUPS) and HBM roofline fraction on
+one MI355X, with the FP64 oracle timed on the host beside it.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload C2|C1]
+
+Workload (default C2): the side-by-side membrane lattice, 4096 x 1024 nodes,
+200 fibres of radius 6 with both catalysts on each fibre, Pe = 100, Da = 5,
+three species (A -> B -> C), FP32 populations with FP64 reductions.  Set-up
+(untimed): geometry, the D2Q9 flow solved to its tolerance (capped), ADR
+initial state, W warm-up steps.  A "step" is one lattice-Boltzmann time step
+of the ADR over the whole lattice (all species: stream, boundary rules,
+collide, link reactions); the timed region runs K steps in blocks of 1000
+captured steps, each block followed by the outlet-flux / efficiency
+evaluation that the convergence loop performs.  MLUPS counts every lattice
+node (solid included) once per step.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "fwd/adjoint LB-ADR MLUPS & %HBM roofline; batched Pe-Da sweep vs serial"
+
+
+def adr_bytes_per_step(node_type, nspecies, real_bytes):
+    """Algorithmic HBM bytes of one ADR step: each fluid node reads and writes
+    its 5*S populations once and reads its 2 velocity components and its 1-byte
+    mask; a solid node reads only its mask."""
+    fluid = int((node_type == 0).sum())
+    solid = node_type.size - fluid
+    per_fluid = 2 * 5 * nspecies * real_bytes + 2 * real_bytes + 1
+    return fluid * per_fluid + solid * 1, per_fluid
+
+
+def flow_bytes_per_step(node_type, real_bytes):
+    fluid = int((node_type == 0).sum())
+    return fluid * (2 * 9 * real_bytes + 2) + (node_type.size - fluid) * 2
+
+
+def kernel_source_hash():
+    path = os.path.join(ROOT, "paper_2109_04455_amd", "csrc", "kernels_adr.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def traffic_from_profiles(workload):
+    """HBM bytes per launch of the ADR kernel from the committed counter
+    summary, or None when it is missing or was taken on other kernel source."""
+    path = os.path.join(ROOT, "profiles", f"adr_step_{workload}_counters.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, steps=20, flow_steps=5):
+    """The oracle as it stands, single-threaded FP64, on the same lattice."""
+    from oracle import lbref as R
+    t = w.node_type
+    ux, uy, _, _ = R.flow_steady(t, w.tau_f, w.u0, flow_steps, tol=0)
+    g = R.adr_init(t, ux, uy, w.nspecies, w.c_in, w.vel_scale)
+    t0 = time.perf_counter()
+    R.adr_run(t, w.k, ux, uy, g, w.tau_g, steps, w.c_in, w.vel_scale)
+    dt = time.perf_counter() - t0
+    return {"value": w.nx * w.ny * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{w.name} lattice {w.nx}x{w.ny}, {w.nspecies} species, {steps} ADR steps "
+                      f"of the FP64 single-threaded oracle ({dt:.1f} s) after {flow_steps} flow steps"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--workload", default="C2")
+    ap.add_argument("--pe", type=float, default=None)
+    ap.add_argument("--flow-max-steps", type=int, default=100000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--probe-copy-mib", type=int, default=1024)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sweep would shard by instance and a large lattice by x-slabs).",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.steps % 1000:
+        args.steps = (args.steps // 1000 + 1) * 1000
+
+    import torch
+    import paper_2109_04455_amd as L
+    from workloads import make_workload
+
+    w = make_workload(args.workload, pe=args.pe)
+    real_bytes = {"f32": 4, "f64": 8}[w.real]
+    p = L.params(w.nx, w.ny, real=w.real, nspecies=w.nspecies, tau_f=w.tau_f, u0=w.u0,
+                 tau_g=w.tau_g, c_in=w.c_in, vel_scale=w.vel_scale)
+    ctx = L.Context(p)
+    ctx.set_geometry(w.node_type)
+    ctx.set_rates(w.k)
+
+    # ---- set-up: flow (a3), handoff + ADR initial state
+    ctx.flow_init()
+    t0 = time.perf_counter()
+    flow_steps, flow_res, flow_conv = ctx.flow_steady(args.flow_max_steps, 1000, w.flow_tol)
+    flow_s = time.perf_counter() - t0
+    flow_ms = ctx.time_flow_steps(1000)
+    flow_mlups = w.nx * w.ny * 1000 / (flow_ms * 1e-3) / 1e6
+    ctx.adr_init()
+    ctx.adr_run(args.warmup, check_every=1000, tol=0)
+
+    # ---- timed region: K ADR steps in blocks of 1000 + efficiency per block
+    torch.cuda.synchronize()
+    kernel_ms = 0.0
+    t0 = time.perf_counter()
+    for _ in range(args.steps // 1000):
+        kernel_ms += ctx.time_adr_steps(1000)
+        eps, N, inflow = ctx.efficiency()
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t0
+
+    nodes = w.nx * w.ny
+    mlups = nodes * args.steps / wall_s / 1e6
+    step_bytes, per_fluid = adr_bytes_per_step(w.node_type, w.nspecies, real_bytes)
+    launch_s = kernel_ms * 1e-3 / args.steps
+    achieved = step_bytes / launch_s / 1e9
+    traffic = traffic_from_profiles(args.workload)
+
+    # practical ceiling: a plain device copy of the same library
+    copy_ms = min(L.probe_copy(args.probe_copy_mib << 20) for _ in range(3))
+    copy_gbs = 2 * (args.probe_copy_mib << 20) / (copy_ms * 1e-3) / 1e9
+
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall_s * 1e3 / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if real_bytes == 4 else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{w.name}: {w.nx}x{w.ny} side-by-side membrane" if w.name == "C2" else
+                        f"{w.name}: {w.nx}x{w.ny}",
+            "nx": w.nx, "ny": w.ny, "nspecies": w.nspecies, "pe": w.params.pe,
+            "da": w.params.da, "tau_g": w.tau_g, "catalytic_nodes": w.n_catalytic(),
+            "check_every": 1000, "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+            "kernel": "k_adr_step<float,3>", "bytes_per_launch": step_bytes,
+            "bytes_per_fluid_node": per_fluid, "avg_launch_us": round(launch_s * 1e6, 3),
+        },
+        "eps": eps, "N": [float(v) for v in N], "inflow": inflow,
+        "flow": {"steps": flow_steps, "residual": flow_res, "converged": flow_conv,
+                 "seconds": round(flow_s, 2), "mlups": round(flow_mlups, 1),
+                 "gbs": round(flow_bytes_per_step(w.node_type, real_bytes) / (flow_ms * 1e-3 / 1000) / 1e9, 1)},
+        "copy_probe_gbs": round(copy_gbs, 1),
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

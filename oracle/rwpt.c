@@ -67,13 +67,40 @@ static double node_u(const geom_t *g, const double *u, int x, int y)
     return u[(size_t)y * g->nx + x];
 }
 
-/* bilinear interpolation of a nodal field at (px, py) */
-static double interp(const geom_t *g, const double *u, double px, double py)
+/* bilinear interpolation of a nodal field at (px, py).  wall_mode 0: solid
+ * nodes carry u = 0 (plain interpolation of the lattice field); wall_mode 1:
+ * a solid corner carries minus the value of the fluid corner(s) next to it
+ * in the cell, so the interpolant vanishes on the wall half-way between the
+ * nodes, where the lattice's bounce-back puts the no-slip wall. */
+static double interp(const geom_t *g, const double *u, double px, double py, int wall_mode)
 {
     int x0 = (int)floor(px), y0 = (int)floor(py);
     double fx = px - x0, fy = py - y0;
-    return (1 - fx) * (1 - fy) * node_u(g, u, x0, y0) + fx * (1 - fy) * node_u(g, u, x0 + 1, y0) +
-           (1 - fx) * fy * node_u(g, u, x0, y0 + 1) + fx * fy * node_u(g, u, x0 + 1, y0 + 1);
+    double v[2][2];
+    int sol[2][2];
+    for (int j = 0; j < 2; ++j)
+        for (int i = 0; i < 2; ++i) {
+            sol[j][i] = solid(g, x0 + i, y0 + j);
+            v[j][i] = sol[j][i] ? 0.0 : node_u(g, u, x0 + i, y0 + j);
+        }
+    if (wall_mode == 1) {
+        double w[2][2];
+        for (int j = 0; j < 2; ++j)
+            for (int i = 0; i < 2; ++i) {
+                w[j][i] = v[j][i];
+                if (!sol[j][i]) continue;
+                double sum = 0;
+                int n = 0;
+                if (!sol[j][1 - i]) { sum -= v[j][1 - i]; ++n; }  /* across a wall normal to x */
+                if (!sol[1 - j][i]) { sum -= v[1 - j][i]; ++n; }  /* across a wall normal to y */
+                if (n == 0 && !sol[1 - j][1 - i]) { sum -= v[1 - j][1 - i]; n = 1; }
+                w[j][i] = n ? sum / n : 0.0;
+            }
+        for (int j = 0; j < 2; ++j)
+            for (int i = 0; i < 2; ++i) v[j][i] = w[j][i];
+    }
+    return (1 - fx) * (1 - fy) * v[0][0] + fx * (1 - fy) * v[0][1] + (1 - fx) * fy * v[1][0] +
+           fx * fy * v[1][1];
 }
 
 /* move from (px,py) to (*qx,*qy) with specular reflection at solid faces */
@@ -112,11 +139,12 @@ static void reflect(const geom_t *g, double px, double py, double *qx, double *q
  *   rate_w      surface rate per unit length = k(sigma) * rate_w
  *   out[0..ns)  net crossings of xf + 1/2 per unit time over the measurement
  *   out[ns]     number of particles in the domain at the end
+ *   wall_mode   velocity interpolation next to solids (see interp)
  */
 int rwpt_run(int nx, int ny, int ns, const uint8_t *type, const double *ux, const double *uy,
              double vel_scale, double D, const double *k, double rate_w, double c_density,
              double dt, double zone, int xf, long burn_steps, long meas_steps, uint64_t seed,
-             long max_particles, double *out)
+             long max_particles, int wall_mode, double *out)
 {
     geom_t g = {nx, ny, type, ux, uy, k, vel_scale, 0.0};
     double step_len = sqrt(4.0 * D * dt);
@@ -168,7 +196,7 @@ int rwpt_run(int nx, int ny, int ns, const uint8_t *type, const double *ux, cons
         }
         for (long j = 0; j < np;) {
             double x0 = px[j], y0 = py[j];
-            double u = vel_scale * interp(&g, ux, x0, y0), v = vel_scale * interp(&g, uy, x0, y0);
+            double u = vel_scale * interp(&g, ux, x0, y0, wall_mode), v = vel_scale * interp(&g, uy, x0, y0, wall_mode);
             double th = 2.0 * M_PI * unif(&r);
             double x1 = x0 + u * dt + step_len * cos(th);
             double y1 = y0 + v * dt + step_len * sin(th);

@@ -32,19 +32,21 @@ def lib():
         d, i, l, p = ctypes.c_double, ctypes.c_int, ctypes.c_long, ctypes.c_void_p
         _lib.rwpt_run.restype = i
         _lib.rwpt_run.argtypes = [i, i, i, p, p, p, d, d, p, d, d, d, d, i, l, l,
-                                  ctypes.c_uint64, l, p]
+                                  ctypes.c_uint64, l, i, p]
     return _lib
 
 
 def run(node_type, ux, uy, k, nspecies, D, *, vel_scale=1.0, rate_w=1.0 / 6.0,
         density=10.0, dt=0.5, zone=1.0, xf=None, burn_steps=10000, meas_steps=20000,
-        seed=1, max_particles=5_000_000):
+        seed=1, max_particles=5_000_000, wall_mode=1):
     """Net crossing rates N_s of the plane xf + 1/2 (particles per unit time).
 
     With ``zone = 1`` and ``rate_w = 1/6`` a particle in the cell of a fluid node
     reacts with probability k(sigma)/6 * dt per catalytic neighbour sigma per
     step -- the lattice link reaction k w_i C read as a first-order sink in the
-    cell adjacent to the catalytic face."""
+    cell adjacent to the catalytic face.  ``wall_mode = 1`` makes the
+    interpolated velocity vanish on the half-way walls of the lattice;
+    ``wall_mode = 0`` interpolates with zero velocity at solid nodes."""
     t = np.ascontiguousarray(node_type, dtype=np.uint8)
     ny, nx = t.shape
     xf = nx - 3 if xf is None else xf
@@ -55,7 +57,7 @@ def run(node_type, ux, uy, k, nspecies, D, *, vel_scale=1.0, rate_w=1.0 / 6.0,
     rc = lib().rwpt_run(nx, ny, nspecies, t.ctypes.data, ux.ctypes.data, uy.ctypes.data,
                         vel_scale, D, k.ctypes.data, rate_w, density, dt, zone, xf,
                         int(burn_steps), int(meas_steps), int(seed), int(max_particles),
-                        out.ctypes.data)
+                        int(wall_mode), out.ctypes.data)
     if rc != 0:
         raise RuntimeError("rwpt_run failed")
     return out[:nspecies]

@@ -1,17 +1,428 @@
-// Adjoint of the ADR step (placeholder until the reverse kernels land).
+// Reverse-mode (adjoint) gradient of the efficiency with respect to the
+// per-node rate k, for catalyst-placement studies.
+//
+// For a frozen velocity field the ADR step is an affine map of the
+// populations.  With g(m) the pre-collision populations and
+// z(m) = R(Col(g(m))) the post-collision ones (R: the link reactions of
+// Eq. source_lbm, Col: the BGK collision), g(m+1) = Str z(m) + b (Str: pull
+// streaming with the bounce-back / anti-bounce-back rules of Eq. BC).  The
+// objective eps = f(N) depends on z(M-1) through the outlet fluxes N.
+// Adjoint variables nu(m) = d eps / d g(m) obey
+//     lambda(m) = Str^T nu(m+1)         (gather from the downstream nodes)
+//     nu(m)     = (R Col)^T lambda(m)   (local, per node)
+// and the gradient collects, for every link (x, i) into a catalytic node
+// sigma = x + c_i with reaction src -> prod,
+//     d eps / d k(sigma) += w_i C_src(x, m) [lambda_prod,i(x,m) - lambda_src,i(x,m)].
+// The transpose needs no forward state except C_src at the fluid nodes next
+// to catalysts (the "trace"), which the forward (or a recomputation from
+// checkpoints) records.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
 #include "ctx.hpp"
+#include "stencil.hpp"
 
 namespace lbf {
+namespace {
+
+enum { DE = 1, DN = 2, DW = 3, DS = 4 };
+constexpr unsigned BIT_E = 1u, BIT_N = 2u, BIT_W = 4u, BIT_S = 8u;
+
+template <typename Real>
+__device__ __forceinline__ Real w5(int i)
+{
+    return i == 0 ? Real(1) / Real(3) : Real(1) / Real(6);
+}
+
+template <typename Real>
+struct AdjArgs {
+    const Real *nu_src;   // nu(m+1) [S][5][plane]
+    Real *nu_dst;         // nu(m)
+    const Real *ua;
+    const uint8_t *mask5;
+    const uint8_t *type;
+    const Real *kr;
+    const int32_t *trace_idx;
+    const Real *trace;    // (C_A, C_B) of step m at the trace nodes
+    double *acc;          // [ntrace][4] per-link gradient accumulators
+    int nx, ny, nxp;
+    size_t plane;
+    Real omega;
+    Launch L;
+};
+
+// One adjoint step at node x for all species.
+template <typename Real, int S>
+__global__ __launch_bounds__(1024) void k_adjoint_step(AdjArgs<Real> a)
+{
+    int x, y;
+    tile_coords(a.L, x, y);
+    if (x >= a.nx || y >= a.ny) return;
+    const size_t id = (size_t)y * a.nxp + x;
+    const unsigned m = a.mask5[id];
+    if (m == MASK5_SOLID) return;
+    const size_t P = a.plane;
+    Real lam[S][5];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const Real *nu = a.nu_src + (size_t)s * 5 * P;
+        lam[s][0] = nu[id];
+        // z_E(x) feeds g_E(x+1), or g_W(x) by bounce-back, or the outlet rule
+        if (x == a.nx - 1)
+            lam[s][DE] = -nu[DW * P + id];
+        else if (m & BIT_E)
+            lam[s][DE] = nu[DW * P + id];
+        else
+            lam[s][DE] = nu[DE * P + id + 1];
+        lam[s][DN] = (m & BIT_N) ? nu[DS * P + id] : nu[DN * P + id + a.nxp];
+        // z_W(x) feeds g_W(x-1), or g_E(x) by bounce-back / the inlet rule
+        if (x == 0)
+            lam[s][DW] = s == 0 ? -nu[DE * P + id] : nu[DE * P + id];
+        else if (m & BIT_W)
+            lam[s][DW] = nu[DE * P + id];
+        else
+            lam[s][DW] = nu[DW * P + id - 1];
+        lam[s][DS] = (m & BIT_S) ? nu[DN * P + id] : nu[DS * P + id - a.nxp];
+        if (x == a.nx - 1) {
+            // outlet: every post-collision population enters C_b of g_W
+            const Real o = Real(2) * w5<Real>(DW) * nu[DW * P + id];
+#pragma unroll
+            for (int i = 0; i < 5; ++i) lam[s][i] += o;
+        }
+    }
+    Real rsrc[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) rsrc[s] = 0;
+    if (m & 0xF0u) {
+        const int off[5] = {0, 1, a.nxp, -1, -a.nxp};
+        const int t = a.trace_idx[id];
+        const Real ca = a.trace[2 * t], cb = a.trace[2 * t + 1];
+#pragma unroll
+        for (int i = 1; i < 5; ++i) {
+            if (!((m >> (3 + i)) & 1u)) continue;
+            const size_t sid = id + off[i];
+            const Real kap = a.kr[sid] * w5<Real>(i);
+            double g;
+            if (a.type[sid] == 2) {
+                const Real d = lam[1][i] - lam[0][i];
+                g = (double)w5<Real>(i) * (double)ca * (double)d;
+                rsrc[0] += kap * d;
+            } else {
+                const Real d = lam[S - 1][i] - lam[1][i];
+                g = (double)w5<Real>(i) * (double)cb * (double)d;
+                rsrc[1] += kap * d;
+            }
+            a.acc[4 * t + i - 1] += g;
+        }
+    }
+    // (R Col)^T: nu_j = (1 - omega) lam_j + omega sum_i e_i lam_i + rsrc
+    const Real u = a.ua[id], v = a.ua[P + id];
+    const Real uu = Real(1.5) * (u * u + v * v);
+    Real e[5];
+    e[0] = w5<Real>(0) * (Real(1) - uu);
+    e[DE] = w5<Real>(DE) * (Real(1) + Real(3) * u + Real(4.5) * u * u - uu);
+    e[DN] = w5<Real>(DN) * (Real(1) + Real(3) * v + Real(4.5) * v * v - uu);
+    e[DW] = w5<Real>(DW) * (Real(1) - Real(3) * u + Real(4.5) * u * u - uu);
+    e[DS] = w5<Real>(DS) * (Real(1) - Real(3) * v + Real(4.5) * v * v - uu);
+    const Real keep = Real(1) - a.omega;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const Real M = e[0] * lam[s][0] + e[1] * lam[s][1] + e[2] * lam[s][2] + e[3] * lam[s][3] +
+                       e[4] * lam[s][4];
+        const Real add = a.omega * M + rsrc[s];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) a.nu_dst[(s * 5 + i) * P + id] = keep * lam[s][i] + add;
+    }
+}
+
+// nu(T) = d eps / d g(T): +dfdN_s on g_E(xf+1), -dfdN_s on g_W(xf), zero
+// elsewhere (the whole lattice is written).
+template <typename Real>
+__global__ void k_adjoint_seed(Real *nu, const uint8_t *mask5, int ns, int nx, int ny, int nxp,
+                               size_t plane, int xf, double d0, double d1, double d2)
+{
+    const size_t n = (size_t)ns * 5 * plane;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const size_t s = i / (5 * plane), q = (i / plane) % 5, id = i % plane;
+        const int x = (int)(id % nxp), y = (int)(id / nxp);
+        Real v = 0;
+        if (y < ny && (x == xf || x == xf + 1)) {
+            const size_t a = (size_t)y * nxp + xf;
+            if (mask5[a] != MASK5_SOLID && mask5[a + 1] != MASK5_SOLID) {
+                const double d = s == 0 ? d0 : (s == 1 ? d1 : d2);
+                if (x == xf + 1 && q == DE) v = Real(d);
+                if (x == xf && q == DW) v = Real(-d);
+            }
+        }
+        nu[i] = v;
+    }
+}
+
+__global__ void k_fill_f64(double *p, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+// grad(sigma) = sum of the link accumulators of the fluid neighbours whose
+// link points at sigma (fixed order E, N, W, S: deterministic).
+__global__ void k_gather_grad(const double *acc, const int32_t *trace_idx, const uint8_t *mask5,
+                              const uint8_t *type, int ns, int nx, int ny, int nxp, double *grad)
+{
+    const size_t n = (size_t)nx * ny;
+    const int off[5] = {0, 1, nxp, -1, -nxp};
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % nx), y = (int)(i / nx);
+        const size_t sid = (size_t)y * nxp + x;
+        const uint8_t t = type[sid];
+        double gsum = 0.0;
+        if (t == 2 || (t == 3 && ns == 3)) {
+            for (int d = 1; d < 5; ++d) {
+                // the fluid node x = sigma - c_d points at sigma along d
+                const int xx = x - (d == 1 ? 1 : d == 3 ? -1 : 0);
+                const int yy = y - (d == 2 ? 1 : d == 4 ? -1 : 0);
+                if (xx < 0 || xx >= nx || yy < 0 || yy >= ny) continue;
+                const size_t fid = sid - off[d];
+                const uint8_t m = mask5[fid];
+                if (m == MASK5_SOLID || !((m >> (3 + d)) & 1u)) continue;
+                gsum += acc[4 * trace_idx[fid] + d - 1];
+            }
+        }
+        grad[i] = gsum;
+    }
+}
+
+template <typename Real>
+AdjArgs<Real> adj_args(Ctx *c, const void *nu_src, void *nu_dst, const void *trace, double *acc)
+{
+    AdjArgs<Real> a{};
+    a.nu_src = (const Real *)nu_src;
+    a.nu_dst = (Real *)nu_dst;
+    a.ua = (const Real *)c->ptr(c->off.ua);
+    a.mask5 = (const uint8_t *)c->ptr(c->off.mask5);
+    a.type = (const uint8_t *)c->ptr(c->off.type);
+    a.kr = (const Real *)c->ptr(c->off.kr);
+    a.trace_idx = (const int32_t *)c->ptr(c->off.trace_idx);
+    a.trace = (const Real *)trace;
+    a.acc = acc;
+    a.nx = c->p.nx;
+    a.ny = c->p.ny;
+    a.nxp = c->nxp;
+    a.plane = c->plane;
+    a.omega = Real(1.0 / c->p.tau_g);
+    a.L = c->L;
+    return a;
+}
+
+hipError_t launch_adjoint_step(Ctx *c, const void *nu_src, void *nu_dst, const void *trace,
+                               double *acc, hipStream_t s)
+{
+    const dim3 g = c->L.grid(), b = c->L.block();
+    if (c->p.real_bytes == 4) {
+        auto a = adj_args<float>(c, nu_src, nu_dst, trace, acc);
+        if (c->p.nspecies == 2)
+            hipLaunchKernelGGL((k_adjoint_step<float, 2>), g, b, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_adjoint_step<float, 3>), g, b, 0, s, a);
+    } else {
+        auto a = adj_args<double>(c, nu_src, nu_dst, trace, acc);
+        if (c->p.nspecies == 2)
+            hipLaunchKernelGGL((k_adjoint_step<double, 2>), g, b, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_adjoint_step<double, 3>), g, b, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+// Forward step between arbitrary lattices (used by the recomputation).
+hipError_t forward_step(Ctx *c, const void *src, void *dst, void *trace, hipStream_t s)
+{
+    AdrArgs<float> af = adr_args<float>(c, 0);
+    AdrArgs<double> ad = adr_args<double>(c, 0);
+    af.src = (const float *)src;
+    af.dst = (float *)dst;
+    af.trace = (float *)trace;
+    ad.src = (const double *)src;
+    ad.dst = (double *)dst;
+    ad.trace = (double *)trace;
+    return launch_adr_step(c->p.real_bytes, c->p.nspecies, trace != nullptr, af, ad, s);
+}
+
+struct AdjLayout {
+    size_t nu[2], rec[2], ckpt, ckpt_trace, trace, acc, total;
+    long nseg;
+    size_t lattice, slot;
+};
+
+AdjLayout adj_layout(const Ctx *c, long T, int M, int keep)
+{
+    AdjLayout L{};
+    const size_t R = c->p.real_bytes;
+    L.lattice = (size_t)c->p.nspecies * 5 * c->plane * R;
+    L.slot = (size_t)std::max(c->ntrace, 1) * 2 * R;
+    L.nseg = (T + M - 1) / M;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    L.nu[0] = take(L.lattice);
+    L.nu[1] = take(L.lattice);
+    L.acc = take((size_t)std::max(c->ntrace, 1) * 4 * sizeof(double));
+    if (keep) {
+        L.trace = take((size_t)T * L.slot);
+        L.rec[0] = L.rec[1] = L.ckpt = L.ckpt_trace = 0;
+    } else {
+        L.rec[0] = take(L.lattice);
+        L.rec[1] = take(L.lattice);
+        L.ckpt = take((size_t)L.nseg * L.lattice);
+        L.ckpt_trace = take((size_t)L.nseg * L.slot);
+        L.trace = take((size_t)M * L.slot);
+    }
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
 void adjoint_release(Ctx *) {}
+
 }  // namespace lbf
 
+using namespace lbf;
+
 extern "C" {
-lbf_status lbf_adjoint_workspace_bytes(lbf_ctx c, long, int, int, size_t *)
+
+lbf_status lbf_adjoint_workspace_bytes(lbf_ctx c, long T, int M, int keep, size_t *bytes)
 {
-    return lbf::fail(c, LBF_EINVAL, "adjoint not implemented yet");
+    if (!c || !bytes) return LBF_EINVAL;
+    if (!c->valid) return fail(c, LBF_EINVAL, "invalid context");
+    if (T < 1 || M < 1) return fail(c, LBF_EINVAL, "need T >= 1 and ckpt_every >= 1");
+    if (!c->geometry_set) return fail(c, LBF_ESTATE, "geometry not set");
+    *bytes = adj_layout(c, T, M, keep).total;
+    return LBF_OK;
 }
-lbf_status lbf_adr_adjoint(lbf_ctx c, long, int, int, void *, size_t, double *, double *)
+
+lbf_status lbf_adr_adjoint(lbf_ctx c, long T, int M, int keep, void *ws, size_t bytes,
+                           double *eps_out, double *grad)
 {
-    return lbf::fail(c, LBF_EINVAL, "adjoint not implemented yet");
+    lbf_status st = check_ready(c, true);
+    if (st != LBF_OK) return st;
+    if (T < 1 || M < 1) return fail(c, LBF_EINVAL, "need T >= 1 and ckpt_every >= 1");
+    if (!ws || !grad) return fail(c, LBF_EINVAL, "NULL workspace or gradient");
+    if ((uintptr_t)ws % 256) return fail(c, LBF_EINVAL, "adjoint workspace must be 256-byte aligned");
+    if (!c->adr_ready || c->adr_steps < 1)
+        return fail(c, LBF_ESTATE, "the adjoint needs at least one ADR step taken");
+    const AdjLayout L = adj_layout(c, T, M, keep);
+    if (bytes < L.total) return fail(c, LBF_ENOMEM, "adjoint workspace too small");
+    char *W = (char *)ws;
+    hipStream_t s = c->stream;
+    double *acc = (double *)(W + L.acc);
+    const size_t nacc = (size_t)std::max(c->ntrace, 1) * 4;
+    hipLaunchKernelGGL(k_fill_f64, dim3(256), dim3(256), 0, s, acc, nacc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "fill");
+
+    auto slot = [&](size_t base, long j) { return (void *)(W + base + (size_t)j * L.slot); };
+    // C at the trace nodes for the window's first step (pre-collision state
+    // pulled from the lattice before the current one)
+    {
+        AdrArgs<float> af = adr_args<float>(c, c->gpar ^ 1);
+        AdrArgs<double> ad = adr_args<double>(c, c->gpar ^ 1);
+        void *s0 = keep ? slot(L.trace, 0) : slot(L.ckpt_trace, 0);
+        af.trace = (float *)s0;
+        ad.trace = (double *)s0;
+        e = launch_trace_conc(c->p.real_bytes, c->p.nspecies, af, ad,
+                              (const int32_t *)c->ptr(c->off.trace_nodes), c->ntrace, s);
+        if (e != hipSuccess) return hip_fail(c, e, "trace at window start");
+    }
+    // ---- forward T steps (as lbf_adr_run would), recording what the reverse needs
+    if (!keep) {
+        e = hipMemcpyAsync(W + L.ckpt, c->ptr(c->off.g[c->gpar]), L.lattice, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(c, e, "checkpoint copy");
+    }
+    for (long m = 1; m <= T; ++m) {
+        void *tr = nullptr;
+        if (keep) {
+            if (m < T) tr = slot(L.trace, m);
+        } else if (m % M == 0 && m < T) {
+            tr = slot(L.ckpt_trace, m / M);
+        }
+        e = enqueue_adr_step(c, c->gpar, s, tr);
+        if (e != hipSuccess) return hip_fail(c, e, "forward step");
+        c->gpar ^= 1;
+        if (!keep && m % M == 0 && m < T) {
+            e = hipMemcpyAsync(W + L.ckpt + (size_t)(m / M) * L.lattice, c->ptr(c->off.g[c->gpar]),
+                               L.lattice, hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return hip_fail(c, e, "checkpoint copy");
+        }
+    }
+    c->adr_steps += T;
+    double o[4];
+    st = compute_fluxes(c, o);
+    if (st != LBF_OK) return st;
+    const int ns = c->p.nspecies;
+    double tot = 0;
+    for (int q = 0; q < ns; ++q) tot += o[q];
+    if (tot == 0) return fail(c, LBF_ESTATE, "total outlet flux is zero: eps undefined");
+    const double eps = o[ns - 1] / tot;
+    double dfdn[3] = {0, 0, 0};
+    for (int q = 0; q < ns; ++q) dfdn[q] = -o[ns - 1] / (tot * tot) + (q == ns - 1 ? 1.0 / tot : 0.0);
+
+    // ---- reverse
+    void *nu[2] = {W + L.nu[0], W + L.nu[1]};
+    if (c->p.real_bytes == 4)
+        hipLaunchKernelGGL(k_adjoint_seed<float>, dim3(2048), dim3(256), 0, s, (float *)nu[0],
+                           (const uint8_t *)c->ptr(c->off.mask5), ns, c->p.nx, c->p.ny, c->nxp,
+                           c->plane, c->xf, dfdn[0], dfdn[1], dfdn[2]);
+    else
+        hipLaunchKernelGGL(k_adjoint_seed<double>, dim3(2048), dim3(256), 0, s, (double *)nu[0],
+                           (const uint8_t *)c->ptr(c->off.mask5), ns, c->p.nx, c->p.ny, c->nxp,
+                           c->plane, c->xf, dfdn[0], dfdn[1], dfdn[2]);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint seed");
+    int cur = 0;
+    if (keep) {
+        for (long m = T - 1; m >= 0; --m) {
+            e = launch_adjoint_step(c, nu[cur], nu[cur ^ 1], slot(L.trace, m), acc, s);
+            if (e != hipSuccess) return hip_fail(c, e, "adjoint step");
+            cur ^= 1;
+        }
+    } else {
+        void *rec[2] = {W + L.rec[0], W + L.rec[1]};
+        for (long j = L.nseg - 1; j >= 0; --j) {
+            const long a0 = j * M, a1 = std::min<long>(T, a0 + M);
+            // segment trace: slot 0 is the checkpoint's, recompute the rest
+            e = hipMemcpyAsync(slot(L.trace, 0), slot(L.ckpt_trace, j), L.slot, hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return hip_fail(c, e, "segment trace copy");
+            const void *src = W + L.ckpt + (size_t)j * L.lattice;
+            int r = 0;
+            for (long q = 1; q < a1 - a0; ++q) {
+                e = forward_step(c, src, rec[r], slot(L.trace, q), s);
+                if (e != hipSuccess) return hip_fail(c, e, "recompute step");
+                src = rec[r];
+                r ^= 1;
+            }
+            for (long m = a1 - 1; m >= a0; --m) {
+                e = launch_adjoint_step(c, nu[cur], nu[cur ^ 1], slot(L.trace, m - a0), acc, s);
+                if (e != hipSuccess) return hip_fail(c, e, "adjoint step");
+                cur ^= 1;
+            }
+        }
+    }
+    hipLaunchKernelGGL(k_gather_grad, dim3(2048), dim3(256), 0, s, acc,
+                       (const int32_t *)c->ptr(c->off.trace_idx), (const uint8_t *)c->ptr(c->off.mask5),
+                       (const uint8_t *)c->ptr(c->off.type), ns, c->p.nx, c->p.ny, c->nxp, grad);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(c, e, "gradient gather");
+    if (eps_out) *eps_out = eps;
+    return LBF_OK;
 }
-}
+
+}  // extern "C"

@@ -61,8 +61,50 @@ lbf_status run_steps(Ctx *c, int kind, long n);
 lbf_status compute_fluxes(Ctx *c, double *out4);
 double efficiency_of(const double *N, int ns);
 hipError_t enqueue_adr_step(Ctx *c, int src_buf, hipStream_t s, void *trace_slot);
-template <typename Real>
-AdrArgs<Real> adr_args(Ctx *c, int src_buf);
 void adjoint_release(Ctx *c);
+
+// Kernel argument blocks for the context's own lattices.
+template <typename Real>
+inline AdrArgs<Real> adr_args(Ctx *c, int src_buf)
+{
+    AdrArgs<Real> a{};
+    a.src = (const Real *)c->ptr(c->off.g[src_buf]);
+    a.dst = (Real *)c->ptr(c->off.g[src_buf ^ 1]);
+    a.ua = (const Real *)c->ptr(c->off.ua);
+    a.mask5 = (const uint8_t *)c->ptr(c->off.mask5);
+    a.type = (const uint8_t *)c->ptr(c->off.type);
+    a.kr = (const Real *)c->ptr(c->off.kr);
+    a.trace_idx = (const int32_t *)c->ptr(c->off.trace_idx);
+    a.trace = nullptr;
+    a.nx = c->p.nx;
+    a.ny = c->p.ny;
+    a.nxp = c->nxp;
+    a.plane = c->plane;
+    a.omega = Real(1.0 / c->p.tau_g);
+    a.cin = Real(c->p.c_in);
+    a.cref = Real(c->cref);
+    a.L = c->L;
+    return a;
+}
+
+template <typename Real>
+inline FlowArgs<Real> flow_args(Ctx *c, int src_buf)
+{
+    FlowArgs<Real> a{};
+    a.src = (const Real *)c->ptr(c->off.f[src_buf]);
+    a.dst = (Real *)c->ptr(c->off.f[src_buf ^ 1]);
+    a.mask9 = (const uint16_t *)c->ptr(c->off.mask9);
+    a.u = (Real *)c->ptr(c->off.u);
+    a.nx = c->p.nx;
+    a.ny = c->p.ny;
+    a.nxp = c->nxp;
+    a.plane = c->plane;
+    a.omega = Real(1.0 / c->p.tau_f);
+    a.u0 = c->p.u0;
+    a.L = c->L;
+    return a;
+}
+
+
 
 }  // namespace lbf
