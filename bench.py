@@ -79,6 +79,67 @@ def cpu_baseline(w, steps=20, flow_steps=5):
                       f"of the FP64 single-threaded oracle ({dt:.1f} s) after {flow_steps} flow steps"}
 
 
+def adjoint_leg(T=20000, M=200):
+    """Adjoint wall time / forward wall time on the C1 geometry (FP32 state,
+    FP64 reductions and gradient), both the checkpoint-recompute path and the
+    path that keeps the whole trace."""
+    import torch
+    import paper_2109_04455_amd as L
+    from workloads import make_workload
+    w = make_workload("C1")
+    p = L.params(w.nx, w.ny, real="f32", nspecies=3, tau_f=w.tau_f, u0=w.u0, tau_g=w.tau_g,
+                 c_in=w.c_in, vel_scale=w.vel_scale)
+    c = L.Context(p)
+    c.set_geometry(w.node_type)
+    c.set_rates(w.k)
+    c.flow_init()
+    c.flow_run(20000)
+    c.adr_init()
+    c.adr_run(20000, tol=0)
+    start = c.get_state()
+    out = {"workload": "C1 geometry (2048x512, 40 fibres), T=%d, checkpoints every %d" % (T, M)}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c.adr_run(T, tol=0)
+    torch.cuda.synchronize()
+    fwd = time.perf_counter() - t0
+    out["forward_s"] = round(fwd, 4)
+    for keep in (False, True):
+        c.set_state(start)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        eps, grad = c.adjoint(T, M, keep_trace=keep)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        tag = "keep_trace" if keep else "recompute"
+        out[f"{tag}_s"] = round(dt, 4)
+        out[f"{tag}_ratio"] = round(dt / fwd, 3)
+        out["eps"] = eps
+        out["grad_max_abs"] = float(grad.abs().max())
+    c.close()
+    return out
+
+
+def batch_leg(steps=2000, flow_steps=2000):
+    """The 64-instance Pe x Da sweep for a fixed number of steps: one batched
+    persistent launch per step vs the same instances run one after another
+    through the single-lattice path (each with its own captured graphs)."""
+    from paper_2109_04455_amd.sweep import sweep_batched, sweep_serial
+    from workloads import batch_instances
+    ws = batch_instances()
+    nodes = sum(w.nx * w.ny for w in ws)
+    b = sweep_batched(ws, flow_steps, steps, check_every=1000)
+    s = sweep_serial(ws, flow_steps, steps, check_every=1000)
+    same = bool((b["product_flux"] == s["product_flux"]).all())
+    return {"instances": len(ws), "nodes": nodes, "steps": steps,
+            "batched_adr_s": round(b["adr_seconds"], 4), "serial_adr_s": round(s["adr_seconds"], 4),
+            "batched_mlups": round(nodes * steps / b["adr_seconds"] / 1e6, 1),
+            "serial_mlups": round(nodes * steps / s["adr_seconds"] / 1e6, 1),
+            "speedup": round(s["adr_seconds"] / b["adr_seconds"], 3),
+            "batched_total_s": round(b["seconds"], 3), "serial_total_s": round(s["seconds"], 3),
+            "identical_results": same}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +150,10 @@ def main():
     ap.add_argument("--flow-max-steps", type=int, default=100000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probe-copy-mib", type=int, default=1024)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=20000)
+    ap.add_argument("--batch-steps", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -164,7 +229,7 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-            "kernel": "k_adr_step<float,3>", "bytes_per_launch": step_bytes,
+            "kernel": "k_adr_step<float,3,false,true>", "bytes_per_launch": step_bytes,
             "bytes_per_fluid_node": per_fluid, "avg_launch_us": round(launch_s * 1e6, 3),
         },
         "eps": eps, "N": [float(v) for v in N], "inflow": inflow,
@@ -174,6 +239,10 @@ def main():
         "copy_probe_gbs": round(copy_gbs, 1),
     }
     ctx.close()
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(args.adjoint_steps)
+    if not args.no_batch:
+        out["batched_sweep"] = batch_leg(args.batch_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

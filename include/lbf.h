@@ -72,11 +72,18 @@ typedef struct {
     double c_in;         /* inlet concentration of A                                 */
     double vel_scale;    /* ADR velocity = vel_scale * flow velocity (linear scaling) */
     int flux_col;        /* outlet flux face between flux_col and flux_col+1; -1: nx-3 */
-    int tile_x, tile_y;  /* thread-block shape of the stencil kernels; 0: default     */
+    int tile_x, tile_y;  /* thread-block shape (threads) of the ADR step; 0: default */
+    int variant;         /* ADR kernel: 0 auto (one node per thread in FP32, 16-byte
+                            vectors of 2 nodes in FP64), 1 one node per thread,
+                            2 16-byte vectors (4 FP32 or 2 FP64 nodes per thread)   */
+    int flags;           /* bit 0: disable the XCD-aware block order; bit 1: cached
+                            instead of streaming (non-temporal) population accesses */
 } lbf_params;
 
 /* Fill *p with defaults for an nx x ny lattice (FP32, 3 species, tau_f 0.8,
- * u0 0.05, tau_g 0.8, c_in 1, vel_scale 1, flux_col -1, default tiles). */
+ * u0 0.05, tau_g 0.8, c_in 1, vel_scale 1, flux_col -1, default tiles
+ * (256x1 nodes, 64x4 for vectors), automatic kernel variant, streaming
+ * accesses, XCD-aware block order). */
 lbf_status lbf_params_default(lbf_params *p, int nx, int ny);
 
 /* Validate the parameters (host only, no HIP call) and create a context. */

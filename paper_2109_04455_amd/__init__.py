@@ -16,7 +16,7 @@ import torch
 from . import _lib
 from ._lib import LbfParams
 
-__all__ = ["LbfError", "LbfNotConverged", "Context", "params", "lib", "probe_copy",
+__all__ = ["LbfError", "LbfNotConverged", "Context", "Batch", "params", "lib", "probe_copy",
            "workspace_tensor"]
 
 
@@ -50,13 +50,14 @@ def _check(status, ctx_handle=None, what=""):
 
 
 def params(nx, ny, *, real="f32", nspecies=3, tau_f=0.8, u0=0.05, tau_g=0.8, c_in=1.0,
-           vel_scale=1.0, flux_col=-1, tile_x=0, tile_y=0) -> LbfParams:
+           vel_scale=1.0, flux_col=-1, tile_x=0, tile_y=0, variant=0, flags=0) -> LbfParams:
     p = LbfParams()
     _check(lib().lbf_params_default(ctypes.byref(p), nx, ny))
     p.real_bytes = {"f32": 4, "f64": 8}[real]
     p.nspecies = nspecies
     p.tau_f, p.u0, p.tau_g, p.c_in, p.vel_scale = tau_f, u0, tau_g, c_in, vel_scale
     p.flux_col, p.tile_x, p.tile_y = flux_col, tile_x, tile_y
+    p.variant, p.flags = variant, flags
     return p
 
 
@@ -245,3 +246,86 @@ def probe_copy(nbytes, device="cuda", stream=None):
     _check(lib().lbf_probe_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
                                 int(nbytes), _stream_handle(s), ctypes.byref(ms)))
     return ms.value
+
+
+class Batch:
+    """Many independent lattices stepped together (the Pe x Da sweep).
+
+    ``plist`` holds one LbfParams per instance (shared precision, species
+    count, tau_f, u0, c_in); geometry and rates are given per instance."""
+
+    def __init__(self, plist, device="cuda", stream=None):
+        self.n = len(plist)
+        self.device = torch.device(device)
+        self.plist = list(plist)
+        arr = (LbfParams * self.n)(*self.plist)
+        h = ctypes.c_void_p()
+        st = lib().lbf_batch_create(self.n, arr, ctypes.byref(h))
+        self._h = h
+        if st != _lib.OK:
+            msg = lib().lbf_batch_last_error(h).decode() if h else ""
+            lib().lbf_batch_destroy(h)
+            self._h = None
+            raise LbfError(st, f"lbf_batch_create: {msg}")
+        nbytes = ctypes.c_size_t()
+        self._call("lbf_batch_workspace_bytes", ctypes.byref(nbytes))
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._ws, ptr = workspace_tensor(nbytes.value, self.device)
+        self._call("lbf_batch_bind", ctypes.c_void_p(ptr), nbytes.value, _stream_handle(self.stream))
+        self.real = {4: torch.float32, 8: torch.float64}[self.plist[0].real_bytes]
+
+    def _call(self, name, *args):
+        st = getattr(lib(), name)(self._h, *args)
+        if st != _lib.OK:
+            msg = lib().lbf_batch_last_error(self._h).decode()
+            cls = LbfNotConverged if st == _lib.ENOTCONV else LbfError
+            raise cls(st, f"{name}: {msg}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            torch.cuda.synchronize(self.device)
+            lib().lbf_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_geometry(self, node_types, rates):
+        t = torch.cat([torch.as_tensor(np.ascontiguousarray(a, dtype=np.uint8)).reshape(-1)
+                       for a in node_types]).to(self.device)
+        k = torch.cat([torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).reshape(-1)
+                       for a in rates]).to(self.device)
+        torch.cuda.synchronize(self.device)
+        self._call("lbf_batch_set_geometry", ctypes.c_void_p(t.data_ptr()),
+                   ctypes.c_void_p(k.data_ptr()))
+
+    def flow(self, max_steps, check_every=1000, tol=0.0):
+        self._call("lbf_batch_flow", int(max_steps), int(check_every), float(tol))
+
+    def run(self, max_steps, check_every=1000, tol=0.0, raise_not_converged=False):
+        """(eps[n], product_flux[n], steps[n]) as numpy arrays."""
+        eps = (ctypes.c_double * self.n)()
+        prod = (ctypes.c_double * self.n)()
+        steps = (ctypes.c_long * self.n)()
+        st = lib().lbf_batch_run(self._h, int(max_steps), int(check_every), float(tol), eps, prod,
+                                 steps)
+        if st != _lib.OK and (st != _lib.ENOTCONV or raise_not_converged):
+            msg = lib().lbf_batch_last_error(self._h).decode()
+            raise LbfError(st, f"lbf_batch_run: {msg}")
+        return np.array(eps[:]), np.array(prod[:]), np.array(steps[:])
+
+    def concentration(self, i, species):
+        p = self.plist[i]
+        out = torch.empty((p.ny, p.nx), dtype=self.real, device=self.device)
+        self._call("lbf_batch_get_concentration", int(i), int(species),
+                   ctypes.c_void_p(out.data_ptr()))
+        torch.cuda.synchronize(self.device)
+        return out
+
+    def time_steps(self, nsteps):
+        ms = ctypes.c_double()
+        self._call("lbf_batch_time_steps", int(nsteps), ctypes.byref(ms))
+        return ms.value

@@ -22,6 +22,7 @@ class LbfParams(ctypes.Structure):
         ("tau_g", ctypes.c_double), ("c_in", ctypes.c_double),
         ("vel_scale", ctypes.c_double),
         ("flux_col", ctypes.c_int), ("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int),
+        ("variant", ctypes.c_int), ("flags", ctypes.c_int),
     ]
 
 

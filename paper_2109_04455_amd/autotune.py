@@ -1,0 +1,72 @@
+"""Small autotuner for the stencil launch: times candidate kernel variants,
+thread-block shapes and cache policies of the ADR step on a representative
+lattice and keeps the fastest, with a JSON cache keyed by (architecture,
+species, precision, nx bucket, ny)."""
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+DEFAULT_CANDIDATES = (
+    # (variant, tile_x, tile_y, flags)
+    (1, 256, 1, 0), (1, 512, 1, 0), (1, 128, 2, 0), (1, 64, 4, 0), (1, 1024, 1, 0),
+    (2, 64, 4, 0), (2, 64, 1, 0), (2, 128, 2, 0),
+    (1, 256, 1, 2),
+)
+
+
+def _key(arch, nspecies, real, nx, ny):
+    bucket = 1 << max(6, (int(nx) - 1).bit_length())
+    return f"{arch}|S{nspecies}|{real}|nx{bucket}|ny{ny}"
+
+
+def _arch():
+    try:
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:
+        return "unknown"
+
+
+def autotune(node_type, k, *, real="f32", nspecies=3, tau_g=0.8, vel_scale=1.0, steps=300,
+             candidates=DEFAULT_CANDIDATES, cache_path=None, verbose=False):
+    """Return (variant, tile_x, tile_y, flags) of the fastest ADR step for this
+    lattice shape.  ``cache_path`` (JSON) is read and updated when given."""
+    import paper_2109_04455_amd as L
+
+    ny, nx = node_type.shape
+    key = _key(_arch(), nspecies, real, nx, ny)
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f)
+        if key in cache:
+            return tuple(cache[key]["best"])
+    results = []
+    for cand in candidates:
+        variant, tx, ty, flags = cand
+        p = L.params(nx, ny, real=real, nspecies=nspecies, tau_g=tau_g, vel_scale=vel_scale,
+                     variant=variant, tile_x=tx, tile_y=ty, flags=flags)
+        try:
+            c = L.Context(p)
+        except L.LbfError:
+            continue
+        c.set_geometry(node_type)
+        c.set_rates(k)
+        c.flow_init()
+        c.flow_run(20)
+        c.adr_init()
+        c.adr_run(20, tol=0)
+        ms = min(c.time_adr_steps(steps) for _ in range(2))
+        c.close()
+        results.append((ms, cand))
+        if verbose:
+            print(f"autotune {key} {cand}: {ms / steps * 1e3:.2f} us/step", flush=True)
+    best = min(results)[1]
+    if cache_path:
+        cache[key] = {"best": list(best),
+                      "timings_us": {str(c): ms / steps * 1e3 for ms, c in results}}
+        with open(cache_path, "w") as f:
+            json.dump(cache, f, indent=1)
+    return best

@@ -53,7 +53,7 @@ struct AdjArgs {
 };
 
 // One adjoint step at node x for all species.
-template <typename Real, int S>
+template <typename Real, int S, bool NT>
 __global__ __launch_bounds__(1024) void k_adjoint_step(AdjArgs<Real> a)
 {
     int x, y;
@@ -67,26 +67,26 @@ __global__ __launch_bounds__(1024) void k_adjoint_step(AdjArgs<Real> a)
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const Real *nu = a.nu_src + (size_t)s * 5 * P;
-        lam[s][0] = nu[id];
+        lam[s][0] = ld<NT>(nu + id);
         // z_E(x) feeds g_E(x+1), or g_W(x) by bounce-back, or the outlet rule
         if (x == a.nx - 1)
-            lam[s][DE] = -nu[DW * P + id];
+            lam[s][DE] = -ld<NT>(nu + DW * P + id);
         else if (m & BIT_E)
-            lam[s][DE] = nu[DW * P + id];
+            lam[s][DE] = ld<NT>(nu + DW * P + id);
         else
-            lam[s][DE] = nu[DE * P + id + 1];
-        lam[s][DN] = (m & BIT_N) ? nu[DS * P + id] : nu[DN * P + id + a.nxp];
+            lam[s][DE] = ld<NT>(nu + DE * P + id + 1);
+        lam[s][DN] = (m & BIT_N) ? ld<NT>(nu + DS * P + id) : ld<NT>(nu + DN * P + id + a.nxp);
         // z_W(x) feeds g_W(x-1), or g_E(x) by bounce-back / the inlet rule
         if (x == 0)
-            lam[s][DW] = s == 0 ? -nu[DE * P + id] : nu[DE * P + id];
+            lam[s][DW] = s == 0 ? -ld<NT>(nu + DE * P + id) : ld<NT>(nu + DE * P + id);
         else if (m & BIT_W)
-            lam[s][DW] = nu[DE * P + id];
+            lam[s][DW] = ld<NT>(nu + DE * P + id);
         else
-            lam[s][DW] = nu[DW * P + id - 1];
-        lam[s][DS] = (m & BIT_S) ? nu[DN * P + id] : nu[DS * P + id - a.nxp];
+            lam[s][DW] = ld<NT>(nu + DW * P + id - 1);
+        lam[s][DS] = (m & BIT_S) ? ld<NT>(nu + DN * P + id) : ld<NT>(nu + DS * P + id - a.nxp);
         if (x == a.nx - 1) {
             // outlet: every post-collision population enters C_b of g_W
-            const Real o = Real(2) * w5<Real>(DW) * nu[DW * P + id];
+            const Real o = Real(2) * w5<Real>(DW) * ld<NT>(nu + DW * P + id);
 #pragma unroll
             for (int i = 0; i < 5; ++i) lam[s][i] += o;
         }
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(1024) void k_adjoint_step(AdjArgs<Real> a)
                        e[4] * lam[s][4];
         const Real add = a.omega * M + rsrc[s];
 #pragma unroll
-        for (int i = 0; i < 5; ++i) a.nu_dst[(s * 5 + i) * P + id] = keep * lam[s][i] + add;
+        for (int i = 0; i < 5; ++i) st<NT>(a.nu_dst + (s * 5 + i) * P + id, keep * lam[s][i] + add);
     }
 }
 
@@ -218,23 +218,31 @@ AdjArgs<Real> adj_args(Ctx *c, const void *nu_src, void *nu_dst, const void *tra
     return a;
 }
 
+template <typename Real>
+void adjoint_launch(Ctx *c, const AdjArgs<Real> &a, hipStream_t s)
+{
+    const dim3 g = c->L.grid(), b = c->L.block();
+    const bool nt = c->L.nontemporal;
+    if (c->p.nspecies == 2) {
+        if (nt)
+            hipLaunchKernelGGL((k_adjoint_step<Real, 2, true>), g, b, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_adjoint_step<Real, 2, false>), g, b, 0, s, a);
+    } else {
+        if (nt)
+            hipLaunchKernelGGL((k_adjoint_step<Real, 3, true>), g, b, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_adjoint_step<Real, 3, false>), g, b, 0, s, a);
+    }
+}
+
 hipError_t launch_adjoint_step(Ctx *c, const void *nu_src, void *nu_dst, const void *trace,
                                double *acc, hipStream_t s)
 {
-    const dim3 g = c->L.grid(), b = c->L.block();
-    if (c->p.real_bytes == 4) {
-        auto a = adj_args<float>(c, nu_src, nu_dst, trace, acc);
-        if (c->p.nspecies == 2)
-            hipLaunchKernelGGL((k_adjoint_step<float, 2>), g, b, 0, s, a);
-        else
-            hipLaunchKernelGGL((k_adjoint_step<float, 3>), g, b, 0, s, a);
-    } else {
-        auto a = adj_args<double>(c, nu_src, nu_dst, trace, acc);
-        if (c->p.nspecies == 2)
-            hipLaunchKernelGGL((k_adjoint_step<double, 2>), g, b, 0, s, a);
-        else
-            hipLaunchKernelGGL((k_adjoint_step<double, 3>), g, b, 0, s, a);
-    }
+    if (c->p.real_bytes == 4)
+        adjoint_launch(c, adj_args<float>(c, nu_src, nu_dst, trace, acc), s);
+    else
+        adjoint_launch(c, adj_args<double>(c, nu_src, nu_dst, trace, acc), s);
     return hipGetLastError();
 }
 
@@ -249,6 +257,7 @@ hipError_t forward_step(Ctx *c, const void *src, void *dst, void *trace, hipStre
     ad.src = (const double *)src;
     ad.dst = (double *)dst;
     ad.trace = (double *)trace;
+    af.L = ad.L = c->Lv;
     return launch_adr_step(c->p.real_bytes, c->p.nspecies, trace != nullptr, af, ad, s);
 }
 

@@ -45,9 +45,13 @@ lbf_status validate_params(const lbf_params *p, std::string &why)
         why = "flux_col must be -1 or in [1, nx-2]";
         return LBF_EINVAL;
     }
-    const int tx = p->tile_x > 0 ? p->tile_x : 64, ty = p->tile_y > 0 ? p->tile_y : 4;
-    if (p->tile_x < 0 || p->tile_y < 0 || tx * ty > 1024 || (tx * ty) % 64 != 0) {
-        why = "tile_x * tile_y must be a multiple of 64 and <= 1024";
+    if (p->variant < 0 || p->variant > 2) { why = "variant must be 0, 1 or 2"; return LBF_EINVAL; }
+    const bool vec = p->variant == 2 || (p->variant == 0 && p->real_bytes == 8);
+    const int tx = p->tile_x > 0 ? p->tile_x : (vec ? 64 : 256);
+    const int ty = p->tile_y > 0 ? p->tile_y : (vec ? 4 : 1);
+    const int maxb = vec ? 256 : 1024;
+    if (p->tile_x < 0 || p->tile_y < 0 || tx * ty > maxb || (tx * ty) % 64 != 0) {
+        why = "tile_x * tile_y must be a multiple of 64 and <= 1024 (<= 256 for vectors)";
         return LBF_EINVAL;
     }
     return LBF_OK;
@@ -92,6 +96,7 @@ hipError_t enqueue_adr_step(Ctx *c, int src_buf, hipStream_t s, void *trace_slot
     AdrArgs<double> ad = adr_args<double>(c, src_buf);
     af.trace = (float *)trace_slot;
     ad.trace = (double *)trace_slot;
+    af.L = ad.L = c->Lv;
     return launch_adr_step(c->p.real_bytes, c->p.nspecies, trace_slot != nullptr, af, ad, s);
 }
 
@@ -250,8 +255,22 @@ lbf_status lbf_create(const lbf_params *p, lbf_ctx *out)
     c->p = *p;
     c->xf = p->flux_col == -1 ? p->nx - 3 : p->flux_col;
     c->cref = p->real_bytes == 4 ? p->c_in : 0.0;
-    c->L = make_launch(p->nx, p->ny, p->tile_x, p->tile_y);
+    c->L = make_launch(p->nx, p->ny, 256, 1);
+    c->L.xcd_remap = !(p->flags & 1);
     layout(c);
+    const bool vec = p->variant == 2 || (p->variant == 0 && p->real_bytes == 8);
+    if (vec) {
+        const int V = 16 / p->real_bytes;
+        c->Lv = make_launch(c->nxp / V, p->ny, p->tile_x > 0 ? p->tile_x : 64,
+                            p->tile_y > 0 ? p->tile_y : 4);
+        c->Lv.vec = true;
+    } else {
+        c->Lv = make_launch(p->nx, p->ny, p->tile_x > 0 ? p->tile_x : 256,
+                            p->tile_y > 0 ? p->tile_y : 1);
+    }
+    c->Lv.xcd_remap = !(p->flags & 1);
+    c->Lv.nontemporal = !(p->flags & 2);
+    c->L.nontemporal = c->Lv.nontemporal;
     c->valid = true;
     return LBF_OK;
 }

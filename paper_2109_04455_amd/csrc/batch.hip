@@ -1,23 +1,674 @@
-// Batched sweep (placeholder until the tile-table kernels land).
-#include "ctx.hpp"
+// Batched Pe x Da sweep: many independent lattices (own geometry, size,
+// tau_g, velocity scale and rates) advanced together.
+//
+// Every instance keeps the single-lattice storage layout inside one
+// workspace.  A tile table lists the (instance, tile) pairs still active; one
+// persistent launch per time step walks the table (each block takes a
+// contiguous chunk of tiles, chunks handed out XCD by XCD), and blocks of
+// steps are captured once and replayed as a HIP graph.  The tile count lives
+// in device memory, so converged instances are dropped from the table by a
+// small compaction kernel without touching the captured graph.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
 
-struct lbf_batch_s {
-    int dummy;
+#include "adr_device.hpp"
+#include "ctx.hpp"
+#include "flow_device.hpp"
+
+namespace lbf {
+namespace {
+
+// Per-instance device descriptor: argument blocks of the single-lattice
+// kernels, for parity 0 (src = lattice 0); parity 1 swaps src and dst.
+template <typename Real>
+struct Inst {
+    AdrArgs<Real> adr;
+    FlowArgs<Real> flow;
+    int tiles_x, tiles_y;  // tile grid of this instance
+    int xf;
+    double cin, cref;
 };
 
-extern "C" {
-lbf_status lbf_batch_create(int, const lbf_params *, lbf_batch *out)
+__device__ __forceinline__ void chunk_of_block(int ntiles, int &t0, int &t1)
 {
-    if (out) *out = nullptr;
-    return LBF_EINVAL;
+    // XCD-aware: blocks on XCD j (h mod 8 == j) take consecutive chunks
+    const int G = gridDim.x, h = blockIdx.x;
+    const int q = G >> 3, r = G & 7, j = h & 7, k = h >> 3;
+    const int b = (G >= 8) ? j * q + (j < r ? j : r) + k : h;
+    t0 = (int)((long long)ntiles * b / G);
+    t1 = (int)((long long)ntiles * (b + 1) / G);
 }
-lbf_status lbf_batch_workspace_bytes(lbf_batch, size_t *) { return LBF_EINVAL; }
-lbf_status lbf_batch_bind(lbf_batch, void *, size_t, void *) { return LBF_EINVAL; }
-lbf_status lbf_batch_set_geometry(lbf_batch, const uint8_t *, const double *) { return LBF_EINVAL; }
-lbf_status lbf_batch_flow(lbf_batch, long, int, double) { return LBF_EINVAL; }
-lbf_status lbf_batch_run(lbf_batch, long, int, double, double *, double *, long *) { return LBF_EINVAL; }
-lbf_status lbf_batch_get_concentration(lbf_batch, int, int, void *) { return LBF_EINVAL; }
-lbf_status lbf_batch_time_steps(lbf_batch, long, double *) { return LBF_EINVAL; }
-const char *lbf_batch_last_error(lbf_batch) { return "batch not implemented yet"; }
-void lbf_batch_destroy(lbf_batch) {}
+
+template <typename Real, int S, bool NT>
+__global__ __launch_bounds__(256) void k_batch_adr(const Inst<Real> *insts, const int4 *tiles,
+                                                   const int *ntiles, int parity, int tx, int ty)
+{
+    int t0, t1;
+    chunk_of_block(*ntiles, t0, t1);
+    for (int t = t0; t < t1; ++t) {
+        const int4 T = tiles[t];
+        AdrArgs<Real> a = insts[T.x].adr;
+        if (parity) {
+            const Real *tmp = a.src;
+            a.src = a.dst;
+            a.dst = const_cast<Real *>(tmp);
+        }
+        const int x = T.y * tx + (int)threadIdx.x % tx;
+        const int y = T.z * ty + (int)threadIdx.x / tx;
+        if (x < a.nx && y < a.ny) adr::node_update<Real, S, false, NT>(a, x, y);
+    }
 }
+
+template <typename Real, bool WRITE_U, bool NT>
+__global__ __launch_bounds__(256) void k_batch_flow(const Inst<Real> *insts, const int4 *tiles,
+                                                    const int *ntiles, int parity, int tx, int ty)
+{
+    int t0, t1;
+    chunk_of_block(*ntiles, t0, t1);
+    for (int t = t0; t < t1; ++t) {
+        const int4 T = tiles[t];
+        FlowArgs<Real> a = insts[T.x].flow;
+        if (parity) {
+            const Real *tmp = a.src;
+            a.src = a.dst;
+            a.dst = const_cast<Real *>(tmp);
+        }
+        const int x = T.y * tx + (int)threadIdx.x % tx;
+        const int y = T.z * ty + (int)threadIdx.x / tx;
+        if (x < a.nx && y < a.ny) flow::node_update<Real, WRITE_U, NT>(a, x, y);
+    }
+}
+
+// Rebuild the tile table from the per-instance active flags (one block).
+template <typename Real>
+__global__ void k_build_tiles(const Inst<Real> *insts, const int *active, int n, int4 *tiles,
+                              int *ntiles)
+{
+    __shared__ int base[1025];
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int i = 0; i < n; ++i) {
+            base[i] = acc;
+            if (active[i]) acc += insts[i].tiles_x * insts[i].tiles_y;
+        }
+        base[n] = acc;
+        *ntiles = acc;
+    }
+    __syncthreads();
+    for (int i = 0; i < n; ++i) {
+        if (!active[i]) continue;
+        const int tx = insts[i].tiles_x, cnt = tx * insts[i].tiles_y;
+        for (int k = threadIdx.x; k < cnt; k += blockDim.x)
+            tiles[base[i] + k] = make_int4(i, k % tx, k / tx, 0);
+    }
+}
+
+// Outlet and inlet fluxes of every instance (one block per instance, the
+// same sums as the single-lattice flux kernel), from lattice `prev_parity`.
+template <typename Real>
+__global__ __launch_bounds__(256) void k_batch_flux(const Inst<Real> *insts, int ns, int prev_parity,
+                                                    double *out)
+{
+    __shared__ double sm[4][256];
+    const Inst<Real> &I = insts[blockIdx.x];
+    const Real *src = prev_parity ? I.adr.dst : I.adr.src;
+    const size_t P = I.adr.plane;
+    const uint8_t *mask5 = I.adr.mask5;
+    double acc[4] = {0, 0, 0, 0};
+    for (int y = threadIdx.x; y < I.adr.ny; y += blockDim.x) {
+        const size_t a = (size_t)y * I.adr.nxp + I.xf, b = a + 1;
+        if (mask5[a] != MASK5_SOLID && mask5[b] != MASK5_SOLID)
+            for (int s = 0; s < ns; ++s)
+                acc[s] += (double)src[(s * 5 + 1) * P + a] - (double)src[(s * 5 + 3) * P + b];
+        const size_t i0 = (size_t)y * I.adr.nxp;
+        if (mask5[i0] != MASK5_SOLID)
+            acc[3] += 2.0 * (1.0 / 6.0) * (I.cin - I.cref) - 2.0 * (double)src[3 * P + i0];
+    }
+    for (int s = 0; s < 4; ++s) sm[s][threadIdx.x] = acc[s];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st)
+            for (int s = 0; s < 4; ++s) sm[s][threadIdx.x] += sm[s][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int s = 0; s < 4; ++s) out[4 * blockIdx.x + s] = sm[s][0];
+}
+
+// max |u - u_prev| of every instance (one block per instance); u -> u_prev.
+template <typename Real>
+__global__ __launch_bounds__(256) void k_batch_du(const Inst<Real> *insts, const int *active,
+                                                  Real *const *uprev, double *out)
+{
+    __shared__ double sm[256];
+    const int i = blockIdx.x;
+    if (!active[i]) {
+        if (threadIdx.x == 0) out[i] = 0.0;
+        return;
+    }
+    const FlowArgs<Real> &F = insts[i].flow;
+    Real *up = uprev[i];
+    double mx = 0.0;
+    for (size_t k = threadIdx.x; k < 2 * F.plane; k += blockDim.x) {
+        const size_t id = k < F.plane ? k : k - F.plane;
+        if (F.mask9[id] & MASK9_SOLID) continue;
+        const double a = (double)F.u[k], b = (double)up[k];
+        double d = fabs(a - b);
+        if (!isfinite(a)) d = INFINITY;
+        mx = fmax(mx, d);
+        up[k] = F.u[k];
+    }
+    sm[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[i] = sm[0];
+}
+
+}  // namespace
+}  // namespace lbf
+
+using namespace lbf;
+
+struct lbf_batch_s {
+    int n = 0;
+    std::vector<lbf_params> p;
+    std::vector<Ctx> ctx;  // per-instance layout and argument builders (no own workspace)
+    std::vector<size_t> base;  // byte offset of each instance's block
+    size_t off_inst = 0, off_tiles = 0, off_ntiles = 0, off_active = 0, off_obs = 0, off_du = 0,
+           off_uprevp = 0, total = 0;
+    int max_tiles = 0;
+    int tx = 256, ty = 1, grid = 2048;
+    char *ws = nullptr;
+    hipStream_t stream = nullptr, cap_stream = nullptr;
+    std::string err;
+    int gpar = 0, fpar = 0;
+    bool geometry = false, flow_done = false;
+    std::map<std::tuple<int, long, int>, hipGraphExec_t> graphs;
+    std::vector<int> parity_of;  // ADR lattice holding each instance's current state
+    std::vector<long> steps_of;
+};
+
+namespace {
+
+lbf_status bfail(lbf_batch b, lbf_status s, const std::string &m)
+{
+    if (b) b->err = m;
+    return s;
+}
+
+lbf_status bhip(lbf_batch b, hipError_t e, const char *what)
+{
+    return bfail(b, LBF_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename Real>
+void fill_insts(lbf_batch b, std::vector<Inst<Real>> &v)
+{
+    v.resize(b->n);
+    for (int i = 0; i < b->n; ++i) {
+        Ctx *c = &b->ctx[i];
+        Inst<Real> I{};
+        I.adr = adr_args<Real>(c, 0);
+        I.flow = flow_args<Real>(c, 0);
+        I.tiles_x = (c->p.nx + b->tx - 1) / b->tx;
+        I.tiles_y = (c->p.ny + b->ty - 1) / b->ty;
+        I.xf = c->xf;
+        I.cin = c->p.c_in;
+        I.cref = c->cref;
+        v[i] = I;
+    }
+}
+
+hipError_t upload_insts(lbf_batch b)
+{
+    if (b->p[0].real_bytes == 4) {
+        std::vector<Inst<float>> v;
+        fill_insts(b, v);
+        hipError_t e = hipMemcpyAsync(b->ws + b->off_inst, v.data(), v.size() * sizeof(v[0]),
+                                      hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        return e;
+    }
+    std::vector<Inst<double>> v;
+    fill_insts(b, v);
+    hipError_t e = hipMemcpyAsync(b->ws + b->off_inst, v.data(), v.size() * sizeof(v[0]),
+                                  hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    return e;
+}
+
+hipError_t set_active(lbf_batch b, const std::vector<int> &act)
+{
+    hipError_t e = hipMemcpyAsync(b->ws + b->off_active, act.data(), act.size() * sizeof(int),
+                                  hipMemcpyHostToDevice, b->stream);
+    if (e != hipSuccess) return e;
+    if (b->p[0].real_bytes == 4)
+        hipLaunchKernelGGL(k_build_tiles<float>, dim3(1), dim3(256), 0, b->stream,
+                           (const Inst<float> *)(b->ws + b->off_inst), (const int *)(b->ws + b->off_active),
+                           b->n, (int4 *)(b->ws + b->off_tiles), (int *)(b->ws + b->off_ntiles));
+    else
+        hipLaunchKernelGGL(k_build_tiles<double>, dim3(1), dim3(256), 0, b->stream,
+                           (const Inst<double> *)(b->ws + b->off_inst), (const int *)(b->ws + b->off_active),
+                           b->n, (int4 *)(b->ws + b->off_tiles), (int *)(b->ws + b->off_ntiles));
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);  // act must outlive the copy
+    return e;
+}
+
+template <typename Real, bool NT>
+void batch_launch(lbf_batch b, int kind, int parity, bool write_u, hipStream_t s)
+{
+    const int4 *tiles = (const int4 *)(b->ws + b->off_tiles);
+    const int *nt = (const int *)(b->ws + b->off_ntiles);
+    const dim3 g(b->grid), blk(b->tx * b->ty);
+    auto I = (const Inst<Real> *)(b->ws + b->off_inst);
+    if (kind == KIND_ADR) {
+        if (b->p[0].nspecies == 2)
+            hipLaunchKernelGGL((k_batch_adr<Real, 2, NT>), g, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
+        else
+            hipLaunchKernelGGL((k_batch_adr<Real, 3, NT>), g, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
+    } else if (write_u) {
+        hipLaunchKernelGGL((k_batch_flow<Real, true, NT>), g, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
+    } else {
+        hipLaunchKernelGGL((k_batch_flow<Real, false, NT>), g, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
+    }
+}
+
+hipError_t enqueue_batch_step(lbf_batch b, int kind, int parity, bool write_u, hipStream_t s)
+{
+    const bool nt = !(b->p[0].flags & 2);
+    if (b->p[0].real_bytes == 4) {
+        if (nt) batch_launch<float, true>(b, kind, parity, write_u, s);
+        else batch_launch<float, false>(b, kind, parity, write_u, s);
+    } else {
+        if (nt) batch_launch<double, true>(b, kind, parity, write_u, s);
+        else batch_launch<double, false>(b, kind, parity, write_u, s);
+    }
+    return hipGetLastError();
+}
+
+// n steps of every active instance (graph replay for long blocks)
+lbf_status batch_steps(lbf_batch b, int kind, long n)
+{
+    int &par = kind == KIND_ADR ? b->gpar : b->fpar;
+    if (n < GRAPH_MIN_STEPS) {
+        for (long i = 0; i < n; ++i) {
+            hipError_t e = enqueue_batch_step(b, kind, par, i == n - 1, b->stream);
+            if (e != hipSuccess) return bhip(b, e, "batched step");
+            par ^= 1;
+        }
+        return LBF_OK;
+    }
+    const auto key = std::make_tuple(kind, n, par);
+    auto it = b->graphs.find(key);
+    if (it == b->graphs.end()) {
+        hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return bhip(b, e, "hipStreamBeginCapture");
+        int p = par;
+        hipError_t le = hipSuccess;
+        for (long i = 0; i < n && le == hipSuccess; ++i) {
+            le = enqueue_batch_step(b, kind, p, i == n - 1, b->cap_stream);
+            p ^= 1;
+        }
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(b->cap_stream, &g);
+        if (le != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return bhip(b, le, "batched step during capture");
+        }
+        if (e != hipSuccess) return bhip(b, e, "hipStreamEndCapture");
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return bhip(b, e, "hipGraphInstantiate");
+        it = b->graphs.emplace(key, ex).first;
+    }
+    hipError_t e = hipGraphLaunch(it->second, b->stream);
+    if (e != hipSuccess) return bhip(b, e, "hipGraphLaunch");
+    if (n & 1) par ^= 1;
+    return LBF_OK;
+}
+
+lbf_status batch_fluxes(lbf_batch b, std::vector<double> &o)
+{
+    o.assign(4 * (size_t)b->n, 0.0);
+    const int prev = b->gpar ^ 1;
+    if (b->p[0].real_bytes == 4)
+        hipLaunchKernelGGL(k_batch_flux<float>, dim3(b->n), dim3(256), 0, b->stream,
+                           (const Inst<float> *)(b->ws + b->off_inst), b->p[0].nspecies, prev,
+                           (double *)(b->ws + b->off_obs));
+    else
+        hipLaunchKernelGGL(k_batch_flux<double>, dim3(b->n), dim3(256), 0, b->stream,
+                           (const Inst<double> *)(b->ws + b->off_inst), b->p[0].nspecies, prev,
+                           (double *)(b->ws + b->off_obs));
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(o.data(), b->ws + b->off_obs, o.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bhip(b, e, "batched flux");
+    return LBF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbf_status lbf_batch_create(int n, const lbf_params *params, lbf_batch *out)
+{
+    if (!out) return LBF_EINVAL;
+    *out = nullptr;
+    if (n < 1 || n > 1024 || !params) return LBF_EINVAL;
+    lbf_batch b = new (std::nothrow) lbf_batch_s();
+    if (!b) return LBF_ENOMEM;
+    *out = b;
+    b->n = n;
+    b->p.assign(params, params + n);
+    b->ctx.resize(n);
+    const lbf_params &p0 = params[0];
+    for (int i = 0; i < n; ++i) {
+        std::string why;
+        const lbf_params &pi = params[i];
+        lbf_status st = validate_params(&pi, why);
+        if (st != LBF_OK) return bfail(b, st, "instance " + std::to_string(i) + ": " + why);
+        if (pi.real_bytes != p0.real_bytes || pi.nspecies != p0.nspecies || pi.tau_f != p0.tau_f ||
+            pi.u0 != p0.u0 || pi.c_in != p0.c_in || pi.reaction_mode != p0.reaction_mode)
+            return bfail(b, LBF_EINVAL, "instances must share real_bytes, nspecies, tau_f, u0, c_in");
+        Ctx &c = b->ctx[i];
+        c.p = pi;
+        c.xf = pi.flux_col == -1 ? pi.nx - 3 : pi.flux_col;
+        c.cref = pi.real_bytes == 4 ? pi.c_in : 0.0;
+        c.L = make_launch(pi.nx, pi.ny, pi.tile_x, pi.tile_y);
+        layout(&c);
+        c.valid = true;
+    }
+    b->tx = p0.tile_x > 0 ? p0.tile_x : 256;
+    b->ty = p0.tile_y > 0 ? p0.tile_y : 1;
+    if (b->tx * b->ty > 256 || (b->tx * b->ty) % 64)
+        return bfail(b, LBF_EINVAL, "batched tiles: tile_x * tile_y must be a multiple of 64, <= 256");
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    b->base.resize(n);
+    int tiles = 0;
+    for (int i = 0; i < n; ++i) {
+        b->base[i] = take(b->ctx[i].ws_need);
+        tiles += ((params[i].nx + b->tx - 1) / b->tx) * ((params[i].ny + b->ty - 1) / b->ty);
+    }
+    b->max_tiles = tiles;
+    const size_t inst_bytes = p0.real_bytes == 4 ? sizeof(Inst<float>) : sizeof(Inst<double>);
+    b->off_inst = take((size_t)n * inst_bytes);
+    b->off_tiles = take((size_t)tiles * sizeof(int4));
+    b->off_ntiles = take(sizeof(int));
+    b->off_active = take((size_t)n * sizeof(int));
+    b->off_obs = take((size_t)n * 4 * sizeof(double));
+    b->off_du = take((size_t)n * sizeof(double));
+    b->off_uprevp = take((size_t)n * sizeof(void *));
+    b->total = off;
+    b->parity_of.assign(n, 0);
+    b->steps_of.assign(n, 0);
+    return LBF_OK;
+}
+
+lbf_status lbf_batch_workspace_bytes(lbf_batch b, size_t *bytes)
+{
+    if (!b || !bytes || b->total == 0) return LBF_EINVAL;
+    *bytes = b->total;
+    return LBF_OK;
+}
+
+lbf_status lbf_batch_bind(lbf_batch b, void *ws, size_t bytes, void *stream)
+{
+    if (!b || b->total == 0) return LBF_EINVAL;
+    if (!ws || (uintptr_t)ws % 256) return bfail(b, LBF_EINVAL, "workspace NULL or not 256-byte aligned");
+    if (bytes < b->total) return bfail(b, LBF_ENOMEM, "workspace smaller than lbf_batch_workspace_bytes");
+    for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+    b->graphs.clear();
+    if (!b->cap_stream) {
+        hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return bhip(b, e, "hipStreamCreate");
+    }
+    b->ws = (char *)ws;
+    b->stream = (hipStream_t)stream;
+    for (int i = 0; i < b->n; ++i) {
+        b->ctx[i].ws = b->ws + b->base[i];
+        b->ctx[i].ws_bytes = b->ctx[i].ws_need;
+        b->ctx[i].stream = b->stream;
+    }
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+        b->grid = cus * 8;
+    hipError_t e = upload_insts(b);
+    if (e != hipSuccess) return bhip(b, e, "upload instance table");
+    std::vector<void *> up(b->n);
+    for (int i = 0; i < b->n; ++i) up[i] = b->ctx[i].ptr(b->ctx[i].off.uprev);
+    e = hipMemcpyAsync(b->ws + b->off_uprevp, up.data(), up.size() * sizeof(void *),
+                       hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bhip(b, e, "upload pointers");
+    b->geometry = b->flow_done = false;
+    return LBF_OK;
+}
+
+lbf_status lbf_batch_set_geometry(lbf_batch b, const uint8_t *type_cat, const double *k_cat)
+{
+    if (!b || !b->ws) return bfail(b, LBF_ESTATE, "no workspace bound");
+    if (!type_cat || !k_cat) return bfail(b, LBF_EINVAL, "NULL input");
+    size_t off = 0;
+    for (int i = 0; i < b->n; ++i) {
+        Ctx *c = &b->ctx[i];
+        lbf_status st = lbf_set_geometry(c, type_cat + off);
+        if (st == LBF_OK) st = lbf_set_rates(c, k_cat + off);
+        if (st != LBF_OK) return bfail(b, st, "instance " + std::to_string(i) + ": " + c->err);
+        off += (size_t)c->p.nx * c->p.ny;
+    }
+    b->geometry = true;
+    return LBF_OK;
+}
+
+lbf_status lbf_batch_flow(lbf_batch b, long max_steps, int check_every, double tol)
+{
+    if (!b || !b->ws || !b->geometry) return bfail(b, LBF_ESTATE, "geometry not set");
+    if (check_every < 1 || max_steps < 0) return bfail(b, LBF_EINVAL, "bad step counts");
+    for (int i = 0; i < b->n; ++i) {
+        Ctx *c = &b->ctx[i];
+        hipError_t e = launch_flow_init(c->p.real_bytes, flow_args<float>(c, 1), flow_args<double>(c, 1),
+                                        b->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->ptr(c->off.uprev), c->ptr(c->off.u), 2 * c->plane * c->p.real_bytes,
+                               hipMemcpyDeviceToDevice, b->stream);
+        if (e != hipSuccess) return bhip(b, e, "flow init");
+    }
+    b->fpar = 0;
+    std::vector<int> act(b->n, 1);
+    hipError_t e = set_active(b, act);
+    if (e != hipSuccess) return bhip(b, e, "tile table");
+    long steps = 0;
+    int nact = b->n;
+    std::vector<double> du(b->n);
+    while (steps < max_steps && nact > 0) {
+        const long n = std::min<long>(check_every, max_steps - steps);
+        for (long left = n; left > 0;) {
+            const long m = std::min<long>(left, 1000);
+            lbf_status st = batch_steps(b, KIND_FLOW, m);
+            if (st != LBF_OK) return st;
+            left -= m;
+        }
+        steps += n;
+        if (tol > 0) {
+            if (b->p[0].real_bytes == 4)
+                hipLaunchKernelGGL(k_batch_du<float>, dim3(b->n), dim3(256), 0, b->stream,
+                                   (const Inst<float> *)(b->ws + b->off_inst), (const int *)(b->ws + b->off_active),
+                                   (float *const *)(b->ws + b->off_uprevp), (double *)(b->ws + b->off_du));
+            else
+                hipLaunchKernelGGL(k_batch_du<double>, dim3(b->n), dim3(256), 0, b->stream,
+                                   (const Inst<double> *)(b->ws + b->off_inst), (const int *)(b->ws + b->off_active),
+                                   (double *const *)(b->ws + b->off_uprevp), (double *)(b->ws + b->off_du));
+            e = hipGetLastError();
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(du.data(), b->ws + b->off_du, du.size() * sizeof(double),
+                                   hipMemcpyDeviceToHost, b->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+            if (e != hipSuccess) return bhip(b, e, "flow residual");
+            bool changed = false;
+            for (int i = 0; i < b->n; ++i) {
+                if (!act[i]) continue;
+                if (!std::isfinite(du[i])) return bfail(b, LBF_EDIVERGED, "non-finite flow velocity");
+                if (n == check_every && du[i] <= tol * std::fabs(b->p[i].u0)) {
+                    act[i] = 0;
+                    --nact;
+                    changed = true;
+                }
+            }
+            if (changed) {
+                e = set_active(b, act);
+                if (e != hipSuccess) return bhip(b, e, "tile table");
+            }
+        }
+    }
+    // every instance's velocity is in its own u buffer (written by the last
+    // step of each block); all instances used the same flow parity sequence
+    e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bhip(b, e, "flow");
+    for (int i = 0; i < b->n; ++i) {
+        b->ctx[i].velocity_set = true;
+        b->ctx[i].flow_ready = true;
+    }
+    b->flow_done = true;
+    return LBF_OK;
+}
+
+lbf_status lbf_batch_run(lbf_batch b, long max_steps, int check_every, double tol, double *eps_host,
+                         double *prod_host, long *steps_host)
+{
+    if (!b || !b->ws || !b->flow_done) return bfail(b, LBF_ESTATE, "run lbf_batch_flow first");
+    if (check_every < 1 || max_steps < 1) return bfail(b, LBF_EINVAL, "bad step counts");
+    const int ns = b->p[0].nspecies;
+    for (int i = 0; i < b->n; ++i) {
+        Ctx *c = &b->ctx[i];
+        hipError_t e = launch_velocity_handoff(c->p.real_bytes, c->ptr(c->off.u), c->ptr(c->off.ua),
+                                               (const uint8_t *)c->ptr(c->off.mask5), c->p.vel_scale,
+                                               c->plane, b->stream);
+        if (e == hipSuccess)
+            e = launch_adr_init(c->p.real_bytes, ns, adr_args<float>(c, 1), adr_args<double>(c, 1),
+                                b->stream);
+        if (e != hipSuccess) return bhip(b, e, "ADR init");
+        c->adr_ready = true;
+        c->gpar = 0;
+    }
+    b->gpar = 0;
+    std::vector<int> act(b->n, 1);
+    hipError_t e = set_active(b, act);
+    if (e != hipSuccess) return bhip(b, e, "tile table");
+    std::vector<double> prev(b->n, NAN), eps(b->n, NAN), prod(b->n, 0.0), o;
+    std::vector<long> steps_i(b->n, 0);
+    long steps = 0;
+    int nact = b->n;
+    while (steps < max_steps && nact > 0) {
+        const long n = std::min<long>(check_every, max_steps - steps);
+        for (long left = n; left > 0;) {
+            const long m = std::min<long>(left, 1000);
+            lbf_status st = batch_steps(b, KIND_ADR, m);
+            if (st != LBF_OK) return st;
+            left -= m;
+        }
+        steps += n;
+        const bool last = steps >= max_steps;
+        if (tol > 0 || last) {
+            lbf_status st = batch_fluxes(b, o);
+            if (st != LBF_OK) return st;
+            bool changed = false;
+            for (int i = 0; i < b->n; ++i) {
+                if (!act[i]) continue;
+                double tot = 0;
+                for (int s = 0; s < ns; ++s) tot += o[4 * i + s];
+                if (!std::isfinite(tot)) return bfail(b, LBF_EDIVERGED, "non-finite flux");
+                const double e_i = tot != 0 ? o[4 * i + ns - 1] / tot : NAN;
+                eps[i] = e_i;
+                prod[i] = o[4 * i + ns - 1];
+                steps_i[i] = steps;
+                b->parity_of[i] = b->gpar;
+                const bool conv = tol > 0 && !std::isnan(prev[i]) && std::fabs(e_i - prev[i]) <= tol * std::fabs(e_i);
+                prev[i] = e_i;
+                if (conv) {
+                    act[i] = 0;
+                    --nact;
+                    changed = true;
+                }
+            }
+            if (changed && nact > 0) {
+                e = set_active(b, act);
+                if (e != hipSuccess) return bhip(b, e, "tile table");
+            }
+        }
+    }
+    for (int i = 0; i < b->n; ++i) {
+        b->ctx[i].gpar = b->parity_of[i];
+        b->ctx[i].adr_steps = steps_i[i];
+        b->steps_of[i] = steps_i[i];
+        if (eps_host) eps_host[i] = eps[i];
+        if (prod_host) prod_host[i] = prod[i];
+        if (steps_host) steps_host[i] = steps_i[i];
+    }
+    if (tol > 0 && nact > 0) return bfail(b, LBF_ENOTCONV, "some instances did not converge");
+    return LBF_OK;
+}
+
+lbf_status lbf_batch_get_concentration(lbf_batch b, int i, int species, void *out)
+{
+    if (!b || i < 0 || i >= b->n) return LBF_EINVAL;
+    lbf_status st = lbf_get_concentration(&b->ctx[i], species, out);
+    if (st != LBF_OK) return bfail(b, st, b->ctx[i].err);
+    return LBF_OK;
+}
+
+lbf_status lbf_batch_time_steps(lbf_batch b, long nsteps, double *ms)
+{
+    if (!b || !b->ws || !b->flow_done) return bfail(b, LBF_ESTATE, "run lbf_batch_flow first");
+    std::vector<int> act(b->n, 1);
+    hipError_t e = set_active(b, act);
+    if (e != hipSuccess) return bhip(b, e, "tile table");
+    hipEvent_t a = nullptr, z = nullptr;
+    e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&z);
+    if (e != hipSuccess) return bhip(b, e, "hipEventCreate");
+    lbf_status st = LBF_OK;
+    e = hipEventRecord(a, b->stream);
+    for (long done = 0; e == hipSuccess && st == LBF_OK && done < nsteps;) {
+        const long m = std::min<long>(1000, nsteps - done);
+        st = batch_steps(b, KIND_ADR, m);
+        done += m;
+    }
+    if (e == hipSuccess) e = hipEventRecord(z, b->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(z);
+    float t = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, a, z);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(z);
+    if (st != LBF_OK) return st;
+    if (e != hipSuccess) return bhip(b, e, "timing");
+    if (ms) *ms = t;
+    return LBF_OK;
+}
+
+const char *lbf_batch_last_error(lbf_batch b) { return b ? b->err.c_str() : "NULL batch"; }
+
+void lbf_batch_destroy(lbf_batch b)
+{
+    if (!b) return;
+    for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    delete b;
+}
+
+}  // extern "C"

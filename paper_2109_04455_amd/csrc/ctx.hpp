@@ -17,7 +17,8 @@ struct lbf_ctx_s {
     size_t plane = 0;  // ny * nxp
     int xf = 0;        // outlet flux column
     double cref = 0;   // storage shift of species A
-    lbf::Launch L;
+    lbf::Launch L;   // one node per thread
+    lbf::Launch Lv;  // ADR step launch (vectorised or not, per params.variant)
 
     // workspace (caller-owned) and its layout
     struct Offsets {
@@ -55,6 +56,8 @@ enum { KIND_ADR = 0, KIND_FLOW = 1 };
 constexpr long GRAPH_MIN_STEPS = 8;
 
 lbf_status fail(Ctx *c, lbf_status s, const std::string &msg);
+lbf_status validate_params(const lbf_params *p, std::string &why);
+void layout(Ctx *c);
 lbf_status hip_fail(Ctx *c, hipError_t e, const char *what);
 lbf_status check_ready(Ctx *c, bool need_geometry);
 lbf_status run_steps(Ctx *c, int kind, long n);

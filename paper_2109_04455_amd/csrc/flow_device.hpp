@@ -1,0 +1,97 @@
+// Per-node device code of the D2Q9 flow step, shared by the single-lattice
+// and the batched kernels.
+#pragma once
+
+#include "stencil.hpp"
+
+namespace lbf {
+namespace flow {
+
+// D2Q9 velocities: rest, E, N, W, S, NE, NW, SW, SE
+constexpr int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+template <typename Real>
+__device__ __forceinline__ Real wgt(int i)
+{
+    return i == 0 ? Real(4) / Real(9) : (i < 5 ? Real(1) / Real(9) : Real(1) / Real(36));
+}
+
+template <typename Real>
+__device__ __forceinline__ Real inlet_u(int y, int ny, double u0)
+{
+    const double h = ny - 2.0;
+    return Real(4.0 * u0 * (y - 0.5) * (ny - 1.5 - y) / (h * h));
+}
+
+// Collide the shifted populations h in place; returns (u, v) and writes them.
+template <typename Real>
+__device__ __forceinline__ void collide(Real (&h)[9], Real omega, Real &u, Real &v)
+{
+    Real drho = 0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) drho += h[i];
+    const Real jx = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
+    const Real jy = (h[2] - h[4]) + (h[5] - h[8]) + (h[6] - h[7]);
+    const Real rho = Real(1) + drho;
+    const Real inv = Real(1) / rho;
+    u = jx * inv;
+    v = jy * inv;
+    const Real uu = Real(1.5) * (u * u + v * v);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const Real cu = Real(CX[i]) * u + Real(CY[i]) * v;
+        // f_eq - w = w (drho + rho (3 cu + 4.5 cu^2 - 1.5 u.u))
+        const Real heq = wgt<Real>(i) * (drho + rho * (Real(3) * cu + Real(4.5) * cu * cu - uu));
+        h[i] -= omega * (h[i] - heq);
+    }
+}
+
+// Full update of node (x, y): gather (bounce-back, Zou-He), collide, store.
+template <typename Real, bool WRITE_U, bool NT = false>
+__device__ __forceinline__ void node_update(const FlowArgs<Real> &a, int x, int y)
+{
+    const size_t id = (size_t)y * a.nxp + x;
+    const unsigned m = a.mask9[id];
+    if (m & MASK9_SOLID) return;
+    const size_t P = a.plane;
+    Real h[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int sx = x - CX[i];
+        if (sx < 0 || sx >= a.nx) {
+            h[i] = 0;  // open boundary: filled by Zou-He below
+        } else if (i != 0 && ((m >> (OPP[i] - 1)) & 1u)) {
+            h[i] = ld<NT>(a.src + OPP[i] * P + id);  // half-way bounce-back
+        } else {
+            h[i] = ld<NT>(a.src + i * P + id - CX[i] - (ptrdiff_t)CY[i] * a.nxp);
+        }
+    }
+    if (x == 0) {
+        // Zou-He velocity inlet, u = (u_in(y), 0): unknown E, NE, SE.
+        // In shifted form the known sum f0+fN+fS+2(fW+fNW+fSW) is 1 + sum h.
+        const Real ux = inlet_u<Real>(y, a.ny, a.u0);
+        const Real rho = (Real(1) + h[0] + h[2] + h[4] + Real(2) * (h[3] + h[6] + h[7])) / (Real(1) - ux);
+        h[1] = h[3] + Real(2) / Real(3) * rho * ux;
+        h[5] = h[7] - Real(0.5) * (h[2] - h[4]) + rho * ux / Real(6);
+        h[8] = h[6] + Real(0.5) * (h[2] - h[4]) + rho * ux / Real(6);
+    } else if (x == a.nx - 1) {
+        // Zou-He pressure outlet, rho = 1, u_y = 0: unknown W, NW, SW
+        const Real ux = h[0] + h[2] + h[4] + Real(2) * (h[1] + h[5] + h[8]);
+        h[3] = h[1] - Real(2) / Real(3) * ux;
+        h[6] = h[8] - Real(0.5) * (h[2] - h[4]) - ux / Real(6);
+        h[7] = h[5] + Real(0.5) * (h[2] - h[4]) - ux / Real(6);
+    }
+    Real u, v;
+    collide(h, a.omega, u, v);
+    if (WRITE_U) {
+        a.u[id] = u;
+        a.u[P + id] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) st<NT>(a.dst + i * P + id, h[i]);
+}
+
+}  // namespace flow
+}  // namespace lbf

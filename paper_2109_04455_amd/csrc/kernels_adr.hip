@@ -17,140 +17,128 @@
 // "Boundary conditions and flux computation in ADE" (Eq. BC, inlet C_A = 1
 // with bounce-back for the other species, outlet C_w = C_b, outflux plane
 // two nodes before the right boundary).
-#include "stencil.hpp"
+#include "adr_device.hpp"
 
 namespace lbf {
 namespace {
 
-// D2Q5: rest, E, N, W, S; w0 = 1/3, w1..4 = 1/6.
-enum { DE = 1, DN = 2, DW = 3, DS = 4 };
-constexpr unsigned BIT_E = 1u, BIT_N = 2u, BIT_W = 4u, BIT_S = 8u;
+using namespace adr;
 
-template <typename Real>
-__device__ __forceinline__ Real w5(int i)
+// 16-byte vectors of V consecutive nodes
+template <typename Real, int V, bool NT = false>
+__device__ __forceinline__ void vload(const Real *p, Real (&o)[V])
 {
-    return i == 0 ? Real(1) / Real(3) : Real(1) / Real(6);
-}
-
-// Gather the pre-collision (shifted) populations of one species at node
-// (x, y) from the post-collision lattice `src` (base of this species).
-template <typename Real>
-__device__ __forceinline__ void pull5(const Real *__restrict__ src, size_t P, size_t id, int x,
-                                      int nx, int nxp, unsigned m, bool species_a, Real inlet_e,
-                                      Real (&h)[5])
-{
-    h[0] = src[id];
-    // E arrives from x - 1
-    if (x == 0)
-        h[DE] = species_a ? inlet_e - src[DW * P + id] : src[DW * P + id];
-    else if (m & BIT_W)
-        h[DE] = src[DW * P + id];
-    else
-        h[DE] = src[DE * P + id - 1];
-    // N arrives from y - 1
-    h[DN] = (m & BIT_S) ? src[DS * P + id] : src[DN * P + id - nxp];
-    // W arrives from x + 1
-    if (x == nx - 1) {
-        const Real sum = src[id] + src[DE * P + id] + src[DN * P + id] + src[DW * P + id] +
-                         src[DS * P + id];
-        h[DW] = Real(2) * w5<Real>(DW) * sum - src[DE * P + id];
-    } else if (m & BIT_E) {
-        h[DW] = src[DE * P + id];
-    } else {
-        h[DW] = src[DW * P + id + 1];
-    }
-    // S arrives from y + 1
-    h[DS] = (m & BIT_N) ? src[DN * P + id] : src[DS * P + id + nxp];
-}
-
-// BGK collision of one species in shifted form (cref = 0 for B and C).
-template <typename Real>
-__device__ __forceinline__ void collide5(Real (&h)[5], Real delta, Real cref, const Real (&p)[5],
-                                         Real omega)
-{
+    typedef Real nv __attribute__((ext_vector_type(V)));
+    const nv v = ld<NT>(reinterpret_cast<const nv *>(p));
 #pragma unroll
-    for (int i = 0; i < 5; ++i) {
-        const Real w = w5<Real>(i);
-        const Real target = w * p[i] * cref + w * (Real(1) + p[i]) * delta;
-        h[i] -= omega * (h[i] - target);
-    }
+    for (int j = 0; j < V; ++j) o[j] = v[j];
 }
 
-template <typename Real>
-__device__ __forceinline__ void eq_factors(Real u, Real v, Real (&p)[5])
+template <typename Real, int V, bool NT = false>
+__device__ __forceinline__ void vstore(Real *p, const Real (&o)[V])
 {
-    const Real uu = Real(1.5) * (u * u + v * v);
-    p[0] = -uu;
-    p[DE] = Real(3) * u + Real(4.5) * u * u - uu;
-    p[DN] = Real(3) * v + Real(4.5) * v * v - uu;
-    p[DW] = -Real(3) * u + Real(4.5) * u * u - uu;
-    p[DS] = -Real(3) * v + Real(4.5) * v * v - uu;
+    typedef Real nv __attribute__((ext_vector_type(V)));
+    nv v;
+#pragma unroll
+    for (int j = 0; j < V; ++j) v[j] = o[j];
+    st<NT>(reinterpret_cast<nv *>(p), v);
 }
 
-// Collide + react + store for one node given its gathered populations.
-template <typename Real, int S, bool TRACE>
-__device__ __forceinline__ void collide_react_store(const AdrArgs<Real> &a, size_t id, unsigned m,
-                                                    Real (&h)[S][5])
+// Vectorised step: each thread owns V consecutive nodes of one row and moves
+// every population array with one 16-byte access per array.  The E (W)
+// populations pulled from x-1 (x+1) come from the aligned vector of the
+// node's own x range plus one scalar element just outside it.  Results are
+// identical to k_adr_step node by node.
+template <typename Real, int S, bool TRACE, int V, bool NT>
+__global__ __launch_bounds__(256) void k_adr_step_vec(AdrArgs<Real> a)
 {
+    int xv, y;
+    tile_coords(a.L, xv, y);
+    const int x0 = xv * V;
+    if (x0 >= a.nx || y >= a.ny) return;
+    const size_t id0 = (size_t)y * a.nxp + x0;
     const size_t P = a.plane;
-    const Real u = a.ua[id], v = a.ua[P + id];
-    Real p[5];
-    eq_factors(u, v, p);
-    Real c[S];
+    unsigned m[V];
+    bool any = false, need_own_s = false, need_own_n = false;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        m[j] = a.mask5[id0 + j];
+        const bool fl = m[j] != MASK5_SOLID;
+        any |= fl;
+        need_own_s |= fl && (m[j] & BIT_S);
+        need_own_n |= fl && (m[j] & BIT_N);
+        need_own_s |= fl && (x0 + j == a.nx - 1);
+        need_own_n |= fl && (x0 + j == a.nx - 1);
+    }
+    if (!any) return;
+    Real ux[V], uy[V];
+    vload<Real, V>(a.ua + id0, ux);
+    vload<Real, V>(a.ua + P + id0, uy);
+    const Real inlet_e = Real(2) * w5<Real>(DE) * (a.cin - a.cref);
+    Real h[S][5][V];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        const Real delta = h[s][0] + h[s][1] + h[s][2] + h[s][3] + h[s][4];
-        const Real cref = s == 0 ? a.cref : Real(0);
-        c[s] = cref + delta;
-        collide5(h[s], delta, cref, p, a.omega);
-    }
-    if (m & 0xF0u) {
-        // link reaction (Eq. source_lbm): the population heading into a
-        // catalytic node loses k w_i C_src, the product gains it
-        const int off[5] = {0, 1, a.nxp, -1, -a.nxp};
+        const Real *src = a.src + (size_t)s * 5 * P;
+        Real own0[V], ownE[V], ownW[V], upN[V], dnS[V], ownN[V] = {}, ownS[V] = {};
+        vload<Real, V, NT>(src + id0, own0);
+        vload<Real, V, NT>(src + DE * P + id0, ownE);
+        vload<Real, V, NT>(src + DW * P + id0, ownW);
+        vload<Real, V, NT>(src + DN * P + id0 - a.nxp, upN);
+        vload<Real, V, NT>(src + DS * P + id0 + a.nxp, dnS);
+        const Real eL = x0 > 0 ? ld<NT>(src + DE * P + id0 - 1) : Real(0);
+        const Real wR = x0 + V < a.nx ? ld<NT>(src + DW * P + id0 + V) : Real(0);
+        if (need_own_n) vload<Real, V, NT>(src + DN * P + id0, ownN);
+        if (need_own_s) vload<Real, V, NT>(src + DS * P + id0, ownS);
 #pragma unroll
-        for (int i = 1; i < 5; ++i) {
-            if (!((m >> (3 + i)) & 1u)) continue;
-            const size_t sid = id + off[i];
-            const Real k = a.kr[sid];
-            if (a.type[sid] == 2) {
-                const Real r = k * w5<Real>(i) * c[0];
-                h[0][i] -= r;
-                h[1][i] += r;
-            } else if (S == 3) {
-                const Real r = k * w5<Real>(i) * c[1];
-                h[1][i] -= r;
-                h[S - 1][i] += r;
+        for (int j = 0; j < V; ++j) {
+            const int x = x0 + j;
+            h[s][0][j] = own0[j];
+            if (x == 0)
+                h[s][DE][j] = s == 0 ? inlet_e - ownW[j] : ownW[j];
+            else if (m[j] & BIT_W)
+                h[s][DE][j] = ownW[j];
+            else
+                h[s][DE][j] = j == 0 ? eL : ownE[j - 1];
+            h[s][DN][j] = (m[j] & BIT_S) ? ownS[j] : upN[j];
+            if (x == a.nx - 1) {
+                const Real sum = own0[j] + ownE[j] + ownN[j] + ownW[j] + ownS[j];
+                h[s][DW][j] = Real(2) * w5<Real>(DW) * sum - ownE[j];
+            } else if (m[j] & BIT_E) {
+                h[s][DW][j] = ownE[j];
+            } else {
+                h[s][DW][j] = j == V - 1 ? wR : ownW[j + 1];
             }
+            h[s][DS][j] = (m[j] & BIT_N) ? ownN[j] : dnS[j];
         }
-        if (TRACE) {
-            const int t = a.trace_idx[id];
-            a.trace[2 * t] = c[0];
-            a.trace[2 * t + 1] = S == 3 ? c[1] : Real(0);
-        }
+    }
+    Real out[S][5][V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        Real hn[S][5];
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int i = 0; i < 5; ++i) hn[s][i] = h[s][i][j];
+        const bool fl = m[j] != MASK5_SOLID;
+        if (fl) collide_react<Real, S, TRACE>(a, id0 + j, m[j], ux[j], uy[j], hn);
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int i = 0; i < 5; ++i) out[s][i][j] = fl ? hn[s][i] : Real(0);
     }
 #pragma unroll
     for (int s = 0; s < S; ++s)
 #pragma unroll
-        for (int i = 0; i < 5; ++i) a.dst[(s * 5 + i) * P + id] = h[s][i];
+        for (int i = 0; i < 5; ++i) vstore<Real, V, NT>(a.dst + (s * 5 + i) * P + id0, out[s][i]);
 }
 
-template <typename Real, int S, bool TRACE>
+template <typename Real, int S, bool TRACE, bool NT>
 __global__ __launch_bounds__(1024) void k_adr_step(AdrArgs<Real> a)
 {
     int x, y;
     tile_coords(a.L, x, y);
     if (x >= a.nx || y >= a.ny) return;
-    const size_t id = (size_t)y * a.nxp + x;
-    const unsigned m = a.mask5[id];
-    if (m == MASK5_SOLID) return;
-    const size_t P = a.plane;
-    const Real inlet_e = Real(2) * w5<Real>(DE) * (a.cin - a.cref);
-    Real h[S][5];
-#pragma unroll
-    for (int s = 0; s < S; ++s)
-        pull5(a.src + (size_t)s * 5 * P, P, id, x, a.nx, a.nxp, m, s == 0, inlet_e, h[s]);
-    collide_react_store<Real, S, TRACE>(a, id, m, h);
+    adr::node_update<Real, S, TRACE, NT>(a, x, y);
 }
 
 // Initial state: A at equilibrium with C = c_in and the ADR velocity, B = C = 0,
@@ -288,20 +276,30 @@ __global__ void k_pad(const Real *src, Real *dst, int nx, int ny, int nxp)
     }
 }
 
+template <typename Real, int S, bool TRACE, bool NT>
+void step_launch(const AdrArgs<Real> &a, hipStream_t s)
+{
+    constexpr int V = 16 / sizeof(Real);
+    if (a.L.vec)
+        hipLaunchKernelGGL((k_adr_step_vec<Real, S, TRACE, V, NT>), a.L.grid(), a.L.block(), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_adr_step<Real, S, TRACE, NT>), a.L.grid(), a.L.block(), 0, s, a);
+}
+
 template <typename Real>
 hipError_t step_dispatch(int ns, bool trace, const AdrArgs<Real> &a, hipStream_t s)
 {
-    const dim3 g = a.L.grid(), b = a.L.block();
+    const bool nt = a.L.nontemporal;
     if (ns == 2) {
         if (trace)
-            hipLaunchKernelGGL((k_adr_step<Real, 2, true>), g, b, 0, s, a);
+            nt ? step_launch<Real, 2, true, true>(a, s) : step_launch<Real, 2, true, false>(a, s);
         else
-            hipLaunchKernelGGL((k_adr_step<Real, 2, false>), g, b, 0, s, a);
+            nt ? step_launch<Real, 2, false, true>(a, s) : step_launch<Real, 2, false, false>(a, s);
     } else {
         if (trace)
-            hipLaunchKernelGGL((k_adr_step<Real, 3, true>), g, b, 0, s, a);
+            nt ? step_launch<Real, 3, true, true>(a, s) : step_launch<Real, 3, true, false>(a, s);
         else
-            hipLaunchKernelGGL((k_adr_step<Real, 3, false>), g, b, 0, s, a);
+            nt ? step_launch<Real, 3, false, true>(a, s) : step_launch<Real, 3, false, false>(a, s);
     }
     return hipGetLastError();
 }

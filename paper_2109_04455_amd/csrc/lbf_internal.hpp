@@ -41,6 +41,8 @@ struct Launch {
     int tx = 64, ty = 4;
     int gx = 1, gy = 1;
     bool xcd_remap = true;
+    bool vec = false;  // ADR step: V nodes per thread (tile covers tx*V nodes in x)
+    bool nontemporal = false;  // streaming loads/stores for the populations
     dim3 grid() const { return dim3(gx * gy, 1, 1); }
     dim3 block() const { return dim3(tx * ty, 1, 1); }
 };

@@ -24,6 +24,27 @@ __device__ __forceinline__ void tile_coords(const Launch &L, int &x, int &y)
     y = by * L.ty + t / L.tx;
 }
 
+// Population loads/stores.  NT selects the non-temporal (streaming) cache
+// policy: every population is touched once per step, so there is nothing to
+// keep in the caches beyond the halo lines shared inside a wavefront.
+template <bool NT, typename Real>
+__device__ __forceinline__ Real ld(const Real *p)
+{
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
+template <bool NT, typename Real>
+__device__ __forceinline__ void st(Real *p, Real v)
+{
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
 inline Launch make_launch(int nx, int ny, int tx, int ty)
 {
     Launch L;

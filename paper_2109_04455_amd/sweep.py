@@ -1,0 +1,63 @@
+"""Pe x Da sweep drivers: all instances through one batched launch per step,
+or one after another through the single-lattice path (the serial baseline)."""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+
+def _params(w, **kw):
+    import paper_2109_04455_amd as L
+    return L.params(w.nx, w.ny, real=w.real, nspecies=w.nspecies, tau_f=w.tau_f, u0=w.u0,
+                    tau_g=w.tau_g, c_in=w.c_in, vel_scale=w.vel_scale, **kw)
+
+
+def sweep_batched(instances, flow_steps, adr_steps, check_every=1000, tol=0.0, flow_tol=0.0,
+                  tile=(256, 1), flags=0):
+    """Returns dict(eps, product_flux, steps, seconds, adr_seconds)."""
+    import paper_2109_04455_amd as L
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = L.Batch([_params(w, tile_x=tile[0], tile_y=tile[1], flags=flags) for w in instances])
+    b.set_geometry([w.node_type for w in instances], [w.k for w in instances])
+    b.flow(flow_steps, check_every=check_every, tol=flow_tol)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    eps, prod, steps = b.run(adr_steps, check_every=check_every, tol=tol)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    b.close()
+    return {"eps": eps, "product_flux": prod, "steps": steps, "seconds": t2 - t0,
+            "adr_seconds": t2 - t1}
+
+
+def sweep_serial(instances, flow_steps, adr_steps, check_every=1000, tol=0.0, flow_tol=0.0,
+                 tile=(256, 1), flags=0):
+    """The same instances one after another, each with its own context and
+    captured graphs."""
+    import paper_2109_04455_amd as L
+    eps, prod, steps = [], [], []
+    adr_s = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for w in instances:
+        c = L.Context(_params(w, tile_x=tile[0], tile_y=tile[1], flags=flags))
+        c.set_geometry(w.node_type)
+        c.set_rates(w.k)
+        c.flow_init()
+        c.flow_steady(flow_steps, check_every, flow_tol)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        c.adr_init()
+        n, _ = c.adr_run(adr_steps, check_every=check_every, tol=tol)
+        e, N, _ = c.efficiency()
+        torch.cuda.synchronize()
+        adr_s += time.perf_counter() - ta
+        eps.append(e)
+        prod.append(N[-1])
+        steps.append(n)
+        c.close()
+    return {"eps": np.array(eps), "product_flux": np.array(prod), "steps": np.array(steps),
+            "seconds": time.perf_counter() - t0, "adr_seconds": adr_s}

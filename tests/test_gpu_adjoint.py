@@ -1,0 +1,116 @@
+"""Adjoint gradient d eps / d k(x) from the GPU against references that do
+not use the GPU: autograd through the PyTorch-CPU twin of the oracle (tiny
+grid), the direct steady-state adjoint (long-window limit), and central
+finite differences of the FP64 GPU forward at seeded catalytic nodes of the
+C1 geometry.  Objective: eps after T steps from the state reached after n0
+steps, that state held fixed."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import lbref as R
+from oracle import torch_ref as TR
+from oracle.steady_direct import System
+from workloads import make_workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(w, real, **kw):
+    import paper_2109_04455_amd as L
+    p = L.params(w.nx, w.ny, real=real, nspecies=w.nspecies, tau_f=w.tau_f, u0=w.u0,
+                 tau_g=w.tau_g, c_in=w.c_in, vel_scale=w.vel_scale, **kw)
+    c = L.Context(p)
+    c.set_geometry(w.node_type)
+    c.set_rates(w.k)
+    return c
+
+
+@pytest.fixture(scope="module")
+def tiny_ref():
+    w = make_workload("tiny")
+    flow_steps, n0, T = 3000, 2000, 1000
+    ux, uy, _, _ = R.flow_steady(w.node_type, w.tau_f, w.u0, flow_steps, tol=0)
+    g0 = R.adr_init(w.node_type, ux, uy, 3)
+    R.adr_run(w.node_type, w.k, ux, uy, g0, w.tau_g, n0)
+    eps, grad, _ = TR.eps_and_grad(w.node_type, w.k, ux, uy, g0, 3, w.tau_g, T)
+    return w, flow_steps, n0, T, eps, grad
+
+
+@pytest.mark.parametrize("real,tol", [("f64", 1e-9), ("f32", 1e-3)])
+@pytest.mark.parametrize("keep,ckpt", [(True, 200), (False, 200), (False, 300)])
+def test_adjoint_matches_autograd(tiny_ref, real, tol, keep, ckpt):
+    w, flow_steps, n0, T, eps_ref, grad_ref = tiny_ref
+    c = _ctx(w, real)
+    c.flow_init()
+    c.flow_run(flow_steps)
+    c.adr_init()
+    c.adr_run(n0, tol=0)
+    eps, grad = c.adjoint(T, ckpt_every=ckpt, keep_trace=keep)
+    grad = grad.cpu().numpy()
+    scale = np.abs(grad_ref).max()
+    assert scale > 0
+    assert np.abs(grad - grad_ref).max() <= tol * scale
+    assert abs(eps / eps_ref - 1) <= tol
+    assert (grad[w.node_type < 2] == 0).all()
+    # the context advanced exactly T steps, as lbf_adr_run(T) would
+    assert c.adr_steps() == n0 + T
+    assert abs(c.efficiency()[0] - eps) <= 1e-12 * abs(eps)
+
+
+def test_adjoint_long_window_tends_to_steady_adjoint():
+    w = make_workload("tiny")
+    ux, uy, _, _ = R.flow_steady(w.node_type, w.tau_f, w.u0, 3000, tol=0)
+    grad_ss, eps_ss = System(w.node_type, w.k, ux, uy, 3, w.tau_g).steady_gradient()
+    c = _ctx(w, "f64")
+    c.flow_init()
+    c.flow_run(3000)
+    c.adr_init()
+    c.adr_run(30000, tol=0)            # converged to round-off
+    eps, grad = c.adjoint(30000, ckpt_every=1000)
+    grad = grad.cpu().numpy()
+    assert abs(eps / eps_ss - 1) < 1e-10
+    assert np.abs(grad - grad_ss).max() < 1e-7 * np.abs(grad_ss).max()
+
+
+def test_adjoint_finite_differences_c1_geometry():
+    # C1 geometry and rates; FP64 forward for the differences (the FP32
+    # per-node signal is below FP32 round-off of eps).  The objective holds
+    # the pre-collision state at the window start fixed, so each difference
+    # restarts from the state one step earlier and re-applies that step's
+    # reaction with the perturbed rate.
+    w = make_workload("C1", real="f64")
+    n0, T = 40000, 20000
+    c = _ctx(w, "f64")
+    c.flow_init()
+    c.flow_run(20000)
+    c.adr_init()
+    c.adr_run(n0 - 1, tol=0)
+    s_prev = c.get_state()
+    c.adr_run(1, tol=0)
+    eps0, grad = c.adjoint(T, ckpt_every=200)
+    grad = grad.cpu().numpy()
+    rng = np.random.default_rng(4)
+    ys, xs = np.nonzero(w.node_type >= 2)
+    pick = list(rng.choice(len(ys), size=16, replace=False))
+    # plus the four nodes with the largest gradient
+    pick += [j for j in np.argsort(-np.abs(grad[ys, xs]))[:4] if j not in pick]
+    fd = []
+    for j in pick:
+        y, x = ys[j], xs[j]
+        h = 1e-3 * w.k[y, x]
+        e = []
+        for sgn in (1, -1):
+            k = w.k.copy()
+            k[y, x] += sgn * h
+            c.set_rates(k)
+            c.set_state(s_prev)
+            c.adr_run(T + 1, tol=0)
+            e.append(c.efficiency()[0])
+        fd.append((e[0] - e[1]) / (2 * h))
+    c.set_rates(w.k)
+    fd = np.array(fd)
+    ad = grad[ys[pick], xs[pick]]
+    scale = np.abs(fd).max()
+    assert scale > 0 and eps0 > 0
+    assert np.abs(ad - fd).max() <= 1e-3 * scale, (ad, fd)

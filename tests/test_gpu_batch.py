@@ -1,0 +1,110 @@
+"""Batched sweep: many uneven instances in one persistent, graph-captured
+launch per step must give the same results as the single-lattice path
+(bit for bit: the per-node arithmetic is the same code) and match the
+oracle; converged instances leave the tile table and keep their state."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import lbref as R
+from workloads import batch_instances, make_workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _params(w, real="f32", **kw):
+    import paper_2109_04455_amd as L
+    return L.params(w.nx, w.ny, real=real, nspecies=w.nspecies, tau_f=w.tau_f, u0=w.u0,
+                    tau_g=w.tau_g, c_in=w.c_in, vel_scale=w.vel_scale, **kw)
+
+
+def _single(w, flow_steps, adr_steps, real="f32"):
+    import paper_2109_04455_amd as L
+    c = L.Context(_params(w, real, variant=1, tile_x=256, tile_y=1))
+    c.set_geometry(w.node_type)
+    c.set_rates(w.k)
+    c.flow_init()
+    c.flow_run(flow_steps)
+    c.adr_init()
+    c.adr_run(adr_steps, tol=0)
+    return c
+
+
+def _instances(n=6, ny=48, seed=5):
+    # small uneven two-membrane cascades with the sweep's Pe/Da draws
+    ws = batch_instances(n=n, seed=seed, ny=ny, nx_range=(200, 400), fibres=2, r=8)
+    return ws
+
+
+@pytest.mark.parametrize("real", ["f32", "f64"])
+def test_batch_equals_single_instance_path(real):
+    import paper_2109_04455_amd as L
+    ws = _instances()
+    b = L.Batch([_params(w, real) for w in ws])
+    b.set_geometry([w.node_type for w in ws], [w.k for w in ws])
+    b.flow(600, check_every=600, tol=0)
+    eps, prod, steps = b.run(1500, check_every=500, tol=0)
+    for i, w in enumerate(ws):
+        c = _single(w, 600, 1500, real)
+        e1, N1, _ = c.efficiency()
+        assert steps[i] == 1500
+        for s in range(3):
+            assert torch.equal(b.concentration(i, s), c.concentration(s)), (i, s)
+        assert eps[i] == e1 or (np.isnan(eps[i]) and np.isnan(e1))
+        assert prod[i] == N1[-1]
+
+
+def test_batch_matches_oracle():
+    import paper_2109_04455_amd as L
+    ws = _instances(n=3, seed=9)
+    b = L.Batch([_params(w, "f64") for w in ws])
+    b.set_geometry([w.node_type for w in ws], [w.k for w in ws])
+    b.flow(500, check_every=500, tol=0)
+    eps, prod, steps = b.run(800, check_every=800, tol=0)
+    for i, w in enumerate(ws):
+        ux, uy, _, _ = R.flow_steady(w.node_type, w.tau_f, w.u0, 500, tol=0)
+        g = R.adr_init(w.node_type, ux, uy, 3, w.c_in, w.vel_scale)
+        R.adr_run(w.node_type, w.k, ux, uy, g, w.tau_g, 800, w.c_in, w.vel_scale)
+        flux, inflow = R.adr_observe(w.node_type, g, w.c_in)
+        c = R.adr_concentration(w.node_type, g)
+        for s in range(3):
+            cg = b.concentration(i, s).cpu().numpy()
+            assert np.abs(cg - c[s]).max() <= 1e-10 * max(np.abs(c[s]).max(), 1e-30)
+        assert abs(prod[i] - flux[-1]) <= 1e-10 * abs(inflow)
+
+
+def test_batch_convergence_drops_instances_and_keeps_their_state():
+    import paper_2109_04455_amd as L
+    # moderate Pe so that most instances converge within the budget
+    ws = batch_instances(n=4, seed=11, ny=48, nx_range=(200, 400), fibres=2, r=8,
+                         pe_range=(5.0, 50.0), da_range=(1.0, 10.0))
+    b = L.Batch([_params(w, "f64") for w in ws])
+    b.set_geometry([w.node_type for w in ws], [w.k for w in ws])
+    b.flow(400, check_every=400, tol=0)
+    budget = 100000
+    eps, prod, steps = b.run(budget, check_every=1000, tol=1e-7)
+    assert (steps < budget).sum() >= 2
+    assert len(set(steps.tolist())) >= 2 or (steps < budget).all()
+    # each instance equals a single-lattice run of exactly its own step count
+    for i, w in enumerate(ws):
+        c = _single(w, 400, int(steps[i]), "f64")
+        e1, N1, inflow = c.efficiency()
+        assert eps[i] == e1
+        assert torch.equal(b.concentration(i, 2), c.concentration(2))
+        if steps[i] < budget:
+            # converged: what flows in leaves as A, B or C
+            assert abs(N1.sum() - inflow) < 1e-4 * inflow
+
+
+def test_sweep_instances_full_size_short():
+    # the 64-instance sweep at full size, a few steps: batch == single path
+    import paper_2109_04455_amd as L
+    ws = batch_instances()
+    b = L.Batch([_params(w) for w in ws])
+    b.set_geometry([w.node_type for w in ws], [w.k for w in ws])
+    b.flow(50, check_every=50, tol=0)
+    eps, prod, steps = b.run(40, check_every=40, tol=0)
+    for i in (0, 17, 63):
+        c = _single(ws[i], 50, 40)
+        assert torch.equal(b.concentration(i, 0), c.concentration(0))
+        assert prod[i] == c.efficiency()[1][-1]

@@ -219,3 +219,36 @@ def test_error_paths_on_device():
     t[0, 5] = 0
     with pytest.raises(L.LbfError):
         c.set_geometry(t)                   # wall row must be solid
+
+
+@pytest.mark.parametrize("name,real", [("C2q", "f32"), ("tiny", "f64"), ("C1q", "f32")])
+def test_vectorised_kernel_equals_one_node_per_thread(name, real):
+    # variant 2: 16-byte vectors of nodes per thread; variant 1: one node per thread
+    w = make_workload(name)
+    out = []
+    for variant in (2, 1):
+        c = _ctx(w, real, variant=variant)
+        c.flow_init()
+        c.flow_run(300)
+        c.adr_init()
+        c.adr_run(700, tol=0)
+        out.append([c.concentration(s) for s in range(w.nspecies)] + [c.efficiency()[0]])
+    for s in range(w.nspecies):
+        a, b = out[0][s], out[1][s]
+        assert torch.equal(a, b) or (a - b).abs().max().item() <= 1e-6 * b.abs().max().item()
+    assert abs(out[0][-1] - out[1][-1]) <= 1e-6 * abs(out[1][-1]) + 1e-300
+
+
+@pytest.mark.parametrize("flags", [0, 2])
+def test_streaming_and_cached_accesses_agree(flags):
+    # the cache policy of the population accesses changes no arithmetic
+    w = make_workload("C1q")
+    out = []
+    for f in (flags, 2 - flags):
+        c = _ctx(w, "f32", flags=f)
+        c.flow_init()
+        c.flow_run(200)
+        c.adr_init()
+        c.adr_run(300, tol=0)
+        out.append(c.concentration(1))
+    assert torch.equal(out[0], out[1])
