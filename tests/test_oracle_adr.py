@@ -181,8 +181,9 @@ def test_plug_flow_uniform_sink():
 def test_da0_outflux_equals_inflow(tiny_flow):
     w, ux, uy = tiny_flow
     z = np.zeros_like(w.k)
-    g, steps, flux, inflow, eps = R.adr_steady(w.node_type, z, ux, uy, 3, w.tau_g, 60000,
-                                               check_every=2000, tol=1e-12)
+    # eps is identically 0 here, so run a fixed number of steps to steady state
+    g, steps, flux, inflow, eps = R.adr_steady(w.node_type, z, ux, uy, 3, w.tau_g, 30000,
+                                               check_every=30000, tol=0)
     assert flux[1] == 0.0 and flux[2] == 0.0 and eps == 0.0
     assert abs(flux[0] - inflow) < 1e-9 * inflow
 
