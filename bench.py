@@ -47,9 +47,15 @@ def flow_bytes_per_step(node_type, real_bytes):
     return fluid * (2 * 9 * real_bytes + 2) + (node_type.size - fluid) * 2
 
 
+ADR_KERNEL_SOURCES = ("kernels_adr.hip", "adr_device.hpp", "stencil.hpp", "lbf_internal.hpp")
+
+
 def kernel_source_hash():
-    path = os.path.join(ROOT, "paper_2109_04455_amd", "csrc", "kernels_adr.hip")
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    """Hash of every source the ADR step kernel is compiled from."""
+    h = hashlib.sha256()
+    for name in ADR_KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2109_04455_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def traffic_from_profiles(workload):
@@ -120,25 +126,60 @@ def adjoint_leg(T=20000, M=200):
     return out
 
 
+def precision_leg(steps=20000, flow_steps=5000):
+    """FP32 path against the FP64 path of the same library on the C1 geometry
+    at a quarter of its linear size, identical step counts: relative error of
+    eps and of the concentration fields (max |dC| / max |C| per species)."""
+    import paper_2109_04455_amd as L
+    from workloads import make_workload
+    w = make_workload("C1q")
+    res = {}
+    for real in ("f32", "f64"):
+        p = L.params(w.nx, w.ny, real=real, nspecies=3, tau_f=w.tau_f, u0=w.u0, tau_g=w.tau_g,
+                     c_in=w.c_in, vel_scale=w.vel_scale)
+        c = L.Context(p)
+        c.set_geometry(w.node_type)
+        c.set_rates(w.k)
+        c.flow_init()
+        c.flow_run(flow_steps)
+        c.adr_init()
+        c.adr_run(steps, tol=0)
+        eps, N, inflow = c.efficiency()
+        res[real] = (eps, [c.concentration(s).double().cpu() for s in range(3)])
+        c.close()
+    e32, c32 = res["f32"]
+    e64, c64 = res["f64"]
+    field = max(float((a - b).abs().max() / b.abs().max()) for a, b in zip(c32, c64))
+    return {"workload": "C1 quarter scale (512x128), %d flow + %d ADR steps" % (flow_steps, steps),
+            "eps_f32": e32, "eps_f64": e64, "eps_rel_err": abs(e32 / e64 - 1),
+            "field_rel_err": field}
+
+
 def batch_leg(steps=2000, flow_steps=2000):
     """The 64-instance Pe x Da sweep for a fixed number of steps: one batched
-    persistent launch per step vs the same instances run one after another
-    through the single-lattice path (each with its own captured graphs)."""
+    launch per step (tile shape and launch mode chosen by the autotuner) vs
+    the same instances run one after another through the single-lattice path
+    (each with its own captured graphs)."""
+    from paper_2109_04455_amd.autotune import autotune_batch
     from paper_2109_04455_amd.sweep import sweep_batched, sweep_serial
     from workloads import batch_instances
     ws = batch_instances()
     nodes = sum(w.nx * w.ny for w in ws)
-    b = sweep_batched(ws, flow_steps, steps, check_every=1000)
+    best, timings = autotune_batch(ws)
+    tile, flags = (best[0], best[1]), best[2]
+    b = sweep_batched(ws, flow_steps, steps, check_every=1000, tile=tile, flags=flags)
     s = sweep_serial(ws, flow_steps, steps, check_every=1000)
     same = bool((b["product_flux"] == s["product_flux"]).all())
     return {"instances": len(ws), "nodes": nodes, "steps": steps,
+            "autotuned": {"tile": list(tile), "mode": "one block per tile" if flags & 8 else
+                          "persistent tile walk",
+                          "us_per_step": {str(k): round(v, 2) for k, v in timings.items()}},
             "batched_adr_s": round(b["adr_seconds"], 4), "serial_adr_s": round(s["adr_seconds"], 4),
             "batched_mlups": round(nodes * steps / b["adr_seconds"] / 1e6, 1),
             "serial_mlups": round(nodes * steps / s["adr_seconds"] / 1e6, 1),
             "speedup": round(s["adr_seconds"] / b["adr_seconds"], 3),
             "batched_total_s": round(b["seconds"], 3), "serial_total_s": round(s["seconds"], 3),
             "identical_results": same}
-
 
 def main():
     ap = argparse.ArgumentParser()
@@ -154,6 +195,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=20000)
     ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--no-precision", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -229,7 +271,7 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-            "kernel": "k_adr_step<float,3,false,true>", "bytes_per_launch": step_bytes,
+            "kernel": "k_adr_step<float,double,3,false,true>", "bytes_per_launch": step_bytes,
             "bytes_per_fluid_node": per_fluid, "avg_launch_us": round(launch_s * 1e6, 3),
         },
         "eps": eps, "N": [float(v) for v in N], "inflow": inflow,
@@ -243,6 +285,8 @@ def main():
         out["adjoint"] = adjoint_leg(args.adjoint_steps)
     if not args.no_batch:
         out["batched_sweep"] = batch_leg(args.batch_steps)
+    if not args.no_precision:
+        out["fp32_vs_fp64"] = precision_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

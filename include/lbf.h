@@ -65,7 +65,12 @@ typedef struct {
     int nx, ny;          /* lattice size incl. wall rows; nx >= 8, ny >= 3           */
     int real_bytes;      /* 4 (FP32 state, FP64 reductions) or 8 (FP64)              */
     int nspecies;        /* 2: A->B, 3: cascade A->B->C                              */
-    int reaction_mode;   /* 0: link reaction (only mode implemented)                 */
+    int reaction_mode;   /* 0: link reaction (only the population streaming into a
+                            catalytic node reacts, rate of that node);  1: the
+                            node variant compared in Sec. "Lattice-Boltzmann for
+                            Advection-Diffusion-Reaction": every population of a
+                            fluid node next to catalysts reacts, with the mean rate
+                            of its catalytic neighbours of each type               */
     double tau_f;        /* D2Q9 relaxation time, > 0.5                              */
     double u0;           /* inlet centre-line velocity of the flow, |u0| < 0.3       */
     double tau_g;        /* D2Q5 relaxation time, > 0.5; D = (tau_g - 1/2)/3         */
@@ -77,13 +82,25 @@ typedef struct {
                             vectors of 2 nodes in FP64), 1 one node per thread,
                             2 16-byte vectors (4 FP32 or 2 FP64 nodes per thread)   */
     int flags;           /* bit 0: disable the XCD-aware block order; bit 1: cached
-                            instead of streaming (non-temporal) population accesses */
+                            instead of streaming (non-temporal) population accesses;
+                            bit 2: store species A unshifted in FP32; bit 3 (batch):
+                            one block per tile instead of the persistent tile walk;
+                            bit 4: FP32 arithmetic for FP32 storage (default: each
+                            node update computes in FP64, rounding once per store);
+                            bit 5: FP32 arithmetic in the flow step only;
+                            bit 6: streaming accesses even when the lattice fits
+                            the 256 MiB last-level cache (default there: cached) */
+    int boundary;        /* 0: channel (solid rows 0 and ny-1, inlet at x = 0,
+                            outlet at x = nx-1); 1: box periodic in x and y with no
+                            inlet or outlet (ADR only: no flow solve, no fluxes,
+                            no adjoint; the velocity comes from lbf_set_velocity) */
 } lbf_params;
 
-/* Fill *p with defaults for an nx x ny lattice (FP32, 3 species, tau_f 0.8,
- * u0 0.05, tau_g 0.8, c_in 1, vel_scale 1, flux_col -1, default tiles
- * (256x1 nodes, 64x4 for vectors), automatic kernel variant, streaming
- * accesses, XCD-aware block order). */
+/* Fill *p with defaults for an nx x ny lattice (FP32, 3 species, link
+ * reactions, channel, tau_f 0.8, u0 0.05, tau_g 0.8, c_in 1, vel_scale 1,
+ * flux_col -1, default tiles (256x1 nodes, 64x4 for vectors), automatic
+ * kernel variant, automatic streaming/cached accesses, XCD-aware block
+ * order). */
 lbf_status lbf_params_default(lbf_params *p, int nx, int ny);
 
 /* Validate the parameters (host only, no HIP call) and create a context. */
@@ -99,7 +116,8 @@ lbf_status lbf_bind(lbf_ctx ctx, void *workspace_dev, size_t bytes, void *hip_st
 
 /* node_type_dev: device uint8 [ny][nx] (copied).  Builds the per-node link
  * masks on the device and the list of fluid nodes next to catalytic nodes.
- * Rows 0 and ny-1 must be solid (LBF_EINVAL otherwise).  Synchronises. */
+ * In a channel rows 0 and ny-1 must be solid (LBF_EINVAL otherwise); a
+ * periodic box wraps the links instead.  Synchronises. */
 lbf_status lbf_set_geometry(lbf_ctx ctx, const uint8_t *node_type_dev);
 
 /* k_dev: device double [ny][nx] (copied); rate of each catalytic node (read
@@ -107,7 +125,8 @@ lbf_status lbf_set_geometry(lbf_ctx ctx, const uint8_t *node_type_dev);
 lbf_status lbf_set_rates(lbf_ctx ctx, const double *k_dev);
 
 /* Flow: initial state f = f_eq(rho = 1, u = (u_in(y), 0)) with the parabola
- * u_in(y) = 4 u0 (y - 1/2)(ny - 3/2 - y)/(ny - 2)^2. */
+ * u_in(y) = 4 u0 (y - 1/2)(ny - 3/2 - y)/(ny - 2)^2.  Channel only
+ * (LBF_EINVAL for a periodic box). */
 lbf_status lbf_flow_init(lbf_ctx ctx);
 /* Advance the flow by exactly nsteps steps (asynchronous). */
 lbf_status lbf_flow_run(lbf_ctx ctx, long nsteps);
@@ -127,17 +146,25 @@ lbf_status lbf_adr_init(lbf_ctx ctx);
 /* Advance up to max_steps; every check_every steps compute eps and stop when
  * |eps - eps_prev| <= tol |eps| (LBF_ENOTCONV when max_steps is reached
  * first).  tol <= 0: run exactly max_steps (asynchronous unless checks are
- * requested).  check_every must be >= 1.  *steps_done may be NULL. */
+ * requested).  check_every must be >= 1.  *steps_done may be NULL.  A
+ * periodic box has no eps: it takes tol <= 0 only (LBF_EINVAL otherwise). */
 lbf_status lbf_adr_run(lbf_ctx ctx, long max_steps, int check_every, double tol,
                        long *steps_done);
 /* Outlet fluxes N[0..nspecies) of the last step (FP64 sums over the rows
  * where both face nodes are fluid), the inflow of A, and eps (Eq. A-B).
  * Requires at least one step (LBF_ESTATE); eps is NaN when sum N = 0.
- * Any output pointer may be NULL.  Synchronises. */
+ * Any output pointer may be NULL.  Channel only.  Synchronises. */
 lbf_status lbf_efficiency(lbf_ctx ctx, double *eps, double *N, double *inflow_A);
 /* Concentration of one species after the last step (zero at solids), Real
  * [ny][nx].  Requires at least one step. */
 lbf_status lbf_get_concentration(lbf_ctx ctx, int species, void *out_dev);
+/* Total amount of each species, totals[0..nspecies) (host double), after the
+ * last step: the FP64 sum of the concentration over the fluid nodes, with a
+ * fixed summation order (bit-reproducible).  In a periodic box with inert
+ * walls sum(totals) is conserved and totals[nspecies-1] measures the
+ * conversion of the time-dependent problem.  Requires at least one step
+ * (LBF_ESTATE).  Synchronises. */
+lbf_status lbf_adr_totals(lbf_ctx ctx, double *totals);
 /* Number of ADR steps taken since lbf_adr_init. */
 lbf_status lbf_adr_steps(lbf_ctx ctx, long *steps);
 
@@ -156,6 +183,19 @@ lbf_status lbf_adjoint_workspace_bytes(lbf_ctx ctx, long T, int ckpt_every, int 
                                        size_t *bytes);
 lbf_status lbf_adr_adjoint(lbf_ctx ctx, long T, int ckpt_every, int keep_trace, void *adj_ws,
                            size_t adj_bytes, double *eps_out, double *grad_k_dev);
+
+/* Steady-state adjoint: d eps / d k of the steady efficiency, for a context
+ * whose ADR state has converged (the caller's responsibility; the current
+ * state is taken as the fixed point).  Iterates the adjoint step with the
+ * steady concentrations until max |nu| <= tol * max |nu_0| (checked every
+ * check_every iterations), summing the gradient of every iteration: the
+ * Neumann series of (I - A^T)^-1.  No forward steps, no checkpoints; the
+ * ADR state is not modified.  adj_ws: lbf_adjoint_workspace_bytes(ctx, 1, 1,
+ * 1, &b) bytes.  LBF_ENOTCONV when max_iters is reached first (gradient of
+ * the partial sum still written).  Synchronises. */
+lbf_status lbf_adr_adjoint_steady(lbf_ctx ctx, long max_iters, int check_every, double tol,
+                                  void *adj_ws, size_t adj_bytes, double *eps_out,
+                                  double *grad_k_dev, long *iters_done);
 
 /* Checkpoint / resume of the ADR state (bit-exact). */
 lbf_status lbf_state_bytes(lbf_ctx ctx, size_t *bytes);

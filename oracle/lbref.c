@@ -169,6 +169,9 @@ void ref_flow_velocity(int nx, int ny, const uint8_t *type, const double *f,
 /* reaction modes */
 #define REF_LINK 0 /* only populations streaming into a catalytic node react */
 #define REF_NODE 1 /* every population of a fluid node reacts (rates k, k2 at the node) */
+#define REF_NODE_AT_CATALYST 2 /* the paper's comparison variant: every population of a
+                                * fluid node next to a catalyst reacts, with the mean rate
+                                * of that node's catalytic neighbours of each type */
 
 static double geq5(int i, double c, double ux, double uy)
 {
@@ -246,6 +249,28 @@ static void adr_step(int nx, int ny, int ns, const uint8_t *type, const double *
                     double r = k[sid] * d5w(i) * c[src];
                     G(post, src, i, id) -= r;
                     G(post, prod, i, id) += r;
+                }
+            } else if (mode == REF_NODE_AT_CATALYST) {
+                double ksum[2] = {0, 0};
+                int kcnt[2] = {0, 0};
+                for (int i = 1; i < 5; ++i) {
+                    int nxx = x + D5X[i], nyy = y + D5Y[i];
+                    if (bc & REF_PERIODIC_X) nxx = wrap(nxx, nx);
+                    if (bc & REF_PERIODIC_Y) nyy = wrap(nyy, ny);
+                    if (nxx < 0 || nxx >= nx || nyy < 0 || nyy >= ny) continue;
+                    size_t sid = (size_t)nyy * nx + nxx;
+                    if (type[sid] == 2) { ksum[0] += k[sid]; kcnt[0]++; }
+                    if (type[sid] == 3 && ns == 3) { ksum[1] += k[sid]; kcnt[1]++; }
+                }
+                for (int q = 0; q < 2; ++q) {
+                    if (kcnt[q] == 0) continue;
+                    int src = q, prod = q + 1;
+                    double kk = ksum[q] / kcnt[q];
+                    for (int i = 0; i < 5; ++i) {
+                        double r = kk * d5w(i) * c[src];
+                        G(post, src, i, id) -= r;
+                        G(post, prod, i, id) += r;
+                    }
                 }
             } else {
                 for (int i = 0; i < 5; ++i) {
@@ -359,4 +384,17 @@ void ref_adr_concentration(int nx, int ny, int ns, const uint8_t *type, const do
                 for (int i = 0; i < 5; ++i) c += g[((size_t)s * 5 + i) * n + id];
             conc[(size_t)s * n + id] = c;
         }
+}
+
+/* Total amount of each species over the fluid nodes (pre-collision). */
+void ref_adr_totals(int nx, int ny, int ns, const uint8_t *type, const double *g, double *tot)
+{
+    size_t n = (size_t)nx * ny;
+    for (int s = 0; s < ns; ++s) {
+        double t = 0.0;
+        for (size_t id = 0; id < n; ++id)
+            if (type[id] == 0)
+                for (int i = 0; i < 5; ++i) t += g[((size_t)s * 5 + i) * n + id];
+        tot[s] = t;
+    }
 }

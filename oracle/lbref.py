@@ -27,6 +27,7 @@ PERIODIC_X = 1
 PERIODIC_Y = 2
 LINK = 0
 NODE = 1
+NODE_AT_CATALYST = 2
 
 _lib = None
 
@@ -59,6 +60,7 @@ def lib():
         _lib.ref_adr_run.argtypes = [i, i, i, p, p, p, p, p, d, d, d, i, i, p, l, p]
         _lib.ref_adr_observe.argtypes = [i, i, i, p, p, d, i, p, p]
         _lib.ref_adr_concentration.argtypes = [i, i, i, p, p, p]
+        _lib.ref_adr_totals.argtypes = [i, i, i, p, p, p]
     return _lib
 
 
@@ -195,3 +197,13 @@ def adr_steady(node_type, k, ux, uy, nspecies, tau, max_steps, check_every=1000,
             break
         prev = eps
     return g, steps, flux, inflow, eps
+
+
+def adr_totals(node_type, g):
+    """Total amount of each species over the fluid nodes."""
+    t = _u8(node_type)
+    ny, nx = t.shape
+    ns = g.shape[0]
+    tot = np.zeros(ns)
+    lib().ref_adr_totals(nx, ny, ns, _ptr(t), _ptr(g), _ptr(tot))
+    return tot

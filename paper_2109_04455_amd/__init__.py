@@ -49,8 +49,13 @@ def _check(status, ctx_handle=None, what=""):
     raise cls(status, msg)
 
 
+LINK, NODE_AT_CATALYST = 0, 1   # reaction_mode
+CHANNEL, PERIODIC = 0, 1         # boundary
+
+
 def params(nx, ny, *, real="f32", nspecies=3, tau_f=0.8, u0=0.05, tau_g=0.8, c_in=1.0,
-           vel_scale=1.0, flux_col=-1, tile_x=0, tile_y=0, variant=0, flags=0) -> LbfParams:
+           vel_scale=1.0, flux_col=-1, tile_x=0, tile_y=0, variant=0, flags=0,
+           reaction_mode=LINK, boundary=CHANNEL) -> LbfParams:
     p = LbfParams()
     _check(lib().lbf_params_default(ctypes.byref(p), nx, ny))
     p.real_bytes = {"f32": 4, "f64": 8}[real]
@@ -58,6 +63,7 @@ def params(nx, ny, *, real="f32", nspecies=3, tau_f=0.8, u0=0.05, tau_g=0.8, c_i
     p.tau_f, p.u0, p.tau_g, p.c_in, p.vel_scale = tau_f, u0, tau_g, c_in, vel_scale
     p.flux_col, p.tile_x, p.tile_y = flux_col, tile_x, tile_y
     p.variant, p.flags = variant, flags
+    p.reaction_mode, p.boundary = reaction_mode, boundary
     return p
 
 
@@ -188,6 +194,12 @@ class Context:
         torch.cuda.current_stream(self.device).wait_stream(self.stream)
         return out
 
+    def totals(self):
+        """Total amount of every species over the fluid nodes (FP64 sums)."""
+        t = (ctypes.c_double * 3)()
+        self._call("lbf_adr_totals", t)
+        return np.array(t[: self.ns])
+
     def adr_steps(self):
         s = ctypes.c_long()
         self._call("lbf_adr_steps", ctypes.byref(s))
@@ -208,6 +220,25 @@ class Context:
                    ctypes.c_void_p(grad.data_ptr()))
         del ws
         return eps.value, grad
+
+    def adjoint_steady(self, max_iters=1_000_000, check_every=1000, tol=1e-12,
+                       raise_not_converged=True):
+        """(eps, grad_k, iterations) of the steady efficiency at the current
+        (converged) state."""
+        nbytes = ctypes.c_size_t()
+        self._call("lbf_adjoint_workspace_bytes", 1, 1, 1, ctypes.byref(nbytes))
+        ws, ptr = workspace_tensor(nbytes.value, self.device)
+        grad = torch.zeros((self.ny, self.nx), dtype=torch.float64, device=self.device)
+        eps = ctypes.c_double()
+        iters = ctypes.c_long()
+        torch.cuda.synchronize(self.device)
+        st = lib().lbf_adr_adjoint_steady(self._h, int(max_iters), int(check_every), float(tol),
+                                          ctypes.c_void_p(ptr), nbytes.value, ctypes.byref(eps),
+                                          ctypes.c_void_p(grad.data_ptr()), ctypes.byref(iters))
+        if st != _lib.ENOTCONV or raise_not_converged:
+            _check(st, self._h, "lbf_adr_adjoint_steady")
+        del ws
+        return eps.value, grad, iters.value
 
     # ----------------------------------------------------- checkpoint/resume
     def get_state(self):

@@ -23,6 +23,7 @@ class LbfParams(ctypes.Structure):
         ("vel_scale", ctypes.c_double),
         ("flux_col", ctypes.c_int), ("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int),
         ("variant", ctypes.c_int), ("flags", ctypes.c_int),
+        ("boundary", ctypes.c_int),
     ]
 
 
@@ -48,9 +49,11 @@ SIGNATURES = {
     "lbf_adr_run": (_I, [_P, _L, _I, _D, _PL]),
     "lbf_efficiency": (_I, [_P, _PD, _PD, _PD]),
     "lbf_get_concentration": (_I, [_P, _I, _P]),
+    "lbf_adr_totals": (_I, [_P, _PD]),
     "lbf_adr_steps": (_I, [_P, _PL]),
     "lbf_adjoint_workspace_bytes": (_I, [_P, _L, _I, _I, _PS]),
     "lbf_adr_adjoint": (_I, [_P, _L, _I, _I, _P, _S, _PD, _P]),
+    "lbf_adr_adjoint_steady": (_I, [_P, _L, _I, _D, _P, _S, _PD, _P, _PL]),
     "lbf_state_bytes": (_I, [_P, _PS]),
     "lbf_get_state": (_I, [_P, _P]),
     "lbf_set_state": (_I, [_P, _P]),

@@ -70,3 +70,39 @@ def autotune(node_type, k, *, real="f32", nspecies=3, tau_g=0.8, vel_scale=1.0, 
         with open(cache_path, "w") as f:
             json.dump(cache, f, indent=1)
     return best
+
+
+BATCH_CANDIDATES = (
+    # (tile_x, tile_y, flags): flags bit 3 = one block per tile
+    (256, 1, 0), (256, 1, 8), (128, 2, 0), (128, 2, 8), (64, 4, 0), (64, 4, 8), (64, 1, 8),
+    (128, 1, 8),
+)
+
+
+def autotune_batch(instances, *, steps=200, flow_steps=20, candidates=BATCH_CANDIDATES,
+                   verbose=False):
+    """Time the batched ADR step over the actual instance set for each
+    candidate (tile shape, persistent tile walk or one block per tile) and
+    return (best_candidate, {candidate: us_per_step})."""
+    import paper_2109_04455_amd as L
+
+    timings = {}
+    for cand in candidates:
+        tx, ty, flags = cand
+        plist = [L.params(w.nx, w.ny, real=w.real, nspecies=w.nspecies, tau_f=w.tau_f, u0=w.u0,
+                          tau_g=w.tau_g, c_in=w.c_in, vel_scale=w.vel_scale, tile_x=tx,
+                          tile_y=ty, flags=flags) for w in instances]
+        try:
+            b = L.Batch(plist)
+        except L.LbfError:
+            continue
+        b.set_geometry([w.node_type for w in instances], [w.k for w in instances])
+        b.flow(flow_steps, check_every=flow_steps, tol=0)
+        b.run(1, check_every=1, tol=0)
+        ms = min(b.time_steps(steps) for _ in range(2))
+        b.close()
+        timings[cand] = ms / steps * 1e3
+        if verbose:
+            print(f"autotune batch {cand}: {timings[cand]:.2f} us/step", flush=True)
+    best = min(timings, key=timings.get)
+    return best, timings

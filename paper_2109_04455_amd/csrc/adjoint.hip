@@ -160,6 +160,26 @@ __global__ void k_adjoint_seed(Real *nu, const uint8_t *mask5, int ns, int nx, i
     }
 }
 
+// max |v| over an array (per-block maxima, then one block); non-finite -> inf
+template <typename Real>
+__global__ __launch_bounds__(256) void k_absmax(const Real *v, size_t n, double *partial)
+{
+    __shared__ double sm[256];
+    double mx = 0.0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const double a = fabs((double)v[i]);
+        mx = fmax(mx, isfinite(a) ? a : INFINITY);
+    }
+    sm[threadIdx.x] = mx;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + st]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sm[0];
+}
+
 __global__ void k_fill_f64(double *p, size_t n)
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -262,7 +282,7 @@ hipError_t forward_step(Ctx *c, const void *src, void *dst, void *trace, hipStre
 }
 
 struct AdjLayout {
-    size_t nu[2], rec[2], ckpt, ckpt_trace, trace, acc, total;
+    size_t nu[2], rec[2], ckpt, ckpt_trace, trace, acc, partial, total;
     long nseg;
     size_t lattice, slot;
 };
@@ -283,6 +303,7 @@ AdjLayout adj_layout(const Ctx *c, long T, int M, int keep)
     L.nu[0] = take(L.lattice);
     L.nu[1] = take(L.lattice);
     L.acc = take((size_t)std::max(c->ntrace, 1) * 4 * sizeof(double));
+    L.partial = take(1025 * sizeof(double));
     if (keep) {
         L.trace = take((size_t)T * L.slot);
         L.rec[0] = L.rec[1] = L.ckpt = L.ckpt_trace = 0;
@@ -311,6 +332,8 @@ lbf_status lbf_adjoint_workspace_bytes(lbf_ctx c, long T, int M, int keep, size_
 {
     if (!c || !bytes) return LBF_EINVAL;
     if (!c->valid) return fail(c, LBF_EINVAL, "invalid context");
+    if (c->p.reaction_mode != 0 || c->p.boundary != 0)
+        return fail(c, LBF_EINVAL, "the adjoint covers link reactions in a channel only");
     if (T < 1 || M < 1) return fail(c, LBF_EINVAL, "need T >= 1 and ckpt_every >= 1");
     if (!c->geometry_set) return fail(c, LBF_ESTATE, "geometry not set");
     *bytes = adj_layout(c, T, M, keep).total;
@@ -322,6 +345,8 @@ lbf_status lbf_adr_adjoint(lbf_ctx c, long T, int M, int keep, void *ws, size_t 
 {
     lbf_status st = check_ready(c, true);
     if (st != LBF_OK) return st;
+    if (c->p.reaction_mode != 0 || c->p.boundary != 0)
+        return fail(c, LBF_EINVAL, "the adjoint covers link reactions in a channel only");
     if (T < 1 || M < 1) return fail(c, LBF_EINVAL, "need T >= 1 and ckpt_every >= 1");
     if (!ws || !grad) return fail(c, LBF_EINVAL, "NULL workspace or gradient");
     if ((uintptr_t)ws % 256) return fail(c, LBF_EINVAL, "adjoint workspace must be 256-byte aligned");
@@ -431,6 +456,110 @@ lbf_status lbf_adr_adjoint(lbf_ctx c, long T, int M, int keep, void *ws, size_t 
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(c, e, "gradient gather");
     if (eps_out) *eps_out = eps;
+    return LBF_OK;
+}
+
+lbf_status lbf_adr_adjoint_steady(lbf_ctx c, long max_iters, int check_every, double tol,
+                                  void *ws, size_t bytes, double *eps_out, double *grad,
+                                  long *iters_done)
+{
+    lbf_status st = check_ready(c, true);
+    if (st != LBF_OK) return st;
+    if (c->p.reaction_mode != 0 || c->p.boundary != 0)
+        return fail(c, LBF_EINVAL, "the adjoint covers link reactions in a channel only");
+    if (max_iters < 1 || check_every < 1 || !(tol > 0))
+        return fail(c, LBF_EINVAL, "need max_iters >= 1, check_every >= 1, tol > 0");
+    if (!ws || !grad) return fail(c, LBF_EINVAL, "NULL workspace or gradient");
+    if ((uintptr_t)ws % 256) return fail(c, LBF_EINVAL, "adjoint workspace must be 256-byte aligned");
+    if (!c->adr_ready || c->adr_steps < 1)
+        return fail(c, LBF_ESTATE, "the steady adjoint needs a (converged) ADR state");
+    const AdjLayout L = adj_layout(c, 1, 1, 1);
+    if (bytes < L.total) return fail(c, LBF_ENOMEM, "adjoint workspace too small");
+    char *W = (char *)ws;
+    hipStream_t s = c->stream;
+    double *acc = (double *)(W + L.acc);
+    hipLaunchKernelGGL(k_fill_f64, dim3(256), dim3(256), 0, s, acc,
+                       (size_t)std::max(c->ntrace, 1) * 4);
+    // the steady concentrations at the trace nodes (constant)
+    void *tr = W + L.trace;
+    {
+        AdrArgs<float> af = adr_args<float>(c, c->gpar ^ 1);
+        AdrArgs<double> ad = adr_args<double>(c, c->gpar ^ 1);
+        af.trace = (float *)tr;
+        ad.trace = (double *)tr;
+        hipError_t e = launch_trace_conc(c->p.real_bytes, c->p.nspecies, af, ad,
+                                         (const int32_t *)c->ptr(c->off.trace_nodes), c->ntrace, s);
+        if (e != hipSuccess) return hip_fail(c, e, "steady trace");
+    }
+    double o[4];
+    st = compute_fluxes(c, o);
+    if (st != LBF_OK) return st;
+    const int ns = c->p.nspecies;
+    double tot = 0;
+    for (int q = 0; q < ns; ++q) tot += o[q];
+    if (tot == 0) return fail(c, LBF_ESTATE, "total outlet flux is zero: eps undefined");
+    const double eps = o[ns - 1] / tot;
+    double dfdn[3] = {0, 0, 0};
+    for (int q = 0; q < ns; ++q) dfdn[q] = -o[ns - 1] / (tot * tot) + (q == ns - 1 ? 1.0 / tot : 0.0);
+    void *nu[2] = {W + L.nu[0], W + L.nu[1]};
+    if (c->p.real_bytes == 4)
+        hipLaunchKernelGGL(k_adjoint_seed<float>, dim3(2048), dim3(256), 0, s, (float *)nu[0],
+                           (const uint8_t *)c->ptr(c->off.mask5), ns, c->p.nx, c->p.ny, c->nxp,
+                           c->plane, c->xf, dfdn[0], dfdn[1], dfdn[2]);
+    else
+        hipLaunchKernelGGL(k_adjoint_seed<double>, dim3(2048), dim3(256), 0, s, (double *)nu[0],
+                           (const uint8_t *)c->ptr(c->off.mask5), ns, c->p.nx, c->p.ny, c->nxp,
+                           c->plane, c->xf, dfdn[0], dfdn[1], dfdn[2]);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint seed");
+    const size_t nlat = (size_t)ns * 5 * c->plane;
+    double *partial = (double *)(W + L.partial);
+    auto absmax = [&](const void *v, double *out) -> lbf_status {
+        if (c->p.real_bytes == 4)
+            hipLaunchKernelGGL(k_absmax<float>, dim3(1024), dim3(256), 0, s, (const float *)v, nlat, partial);
+        else
+            hipLaunchKernelGGL(k_absmax<double>, dim3(1024), dim3(256), 0, s, (const double *)v, nlat, partial);
+        hipError_t e2 = hipGetLastError();
+        if (e2 == hipSuccess) e2 = launch_du_max_partials(partial, 1024, partial + 1024, s);
+        double h = 0;
+        if (e2 == hipSuccess) e2 = hipMemcpyAsync(&h, partial + 1024, sizeof h, hipMemcpyDeviceToHost, s);
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+        if (e2 != hipSuccess) return hip_fail(c, e2, "adjoint norm");
+        *out = h;
+        return LBF_OK;
+    };
+    double n0 = 0;
+    st = absmax(nu[0], &n0);
+    if (st != LBF_OK) return st;
+    int cur = 0;
+    long it = 0;
+    bool conv = false;
+    while (it < max_iters) {
+        const long m = std::min<long>(check_every, max_iters - it);
+        for (long q = 0; q < m; ++q) {
+            e = launch_adjoint_step(c, nu[cur], nu[cur ^ 1], tr, acc, s);
+            if (e != hipSuccess) return hip_fail(c, e, "adjoint step");
+            cur ^= 1;
+        }
+        it += m;
+        double nn = 0;
+        st = absmax(nu[cur], &nn);
+        if (st != LBF_OK) return st;
+        if (!std::isfinite(nn)) return fail(c, LBF_EDIVERGED, "adjoint diverged");
+        if (nn <= tol * n0) {
+            conv = true;
+            break;
+        }
+    }
+    hipLaunchKernelGGL(k_gather_grad, dim3(2048), dim3(256), 0, s, acc,
+                       (const int32_t *)c->ptr(c->off.trace_idx), (const uint8_t *)c->ptr(c->off.mask5),
+                       (const uint8_t *)c->ptr(c->off.type), ns, c->p.nx, c->p.ny, c->nxp, grad);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(c, e, "gradient gather");
+    if (eps_out) *eps_out = eps;
+    if (iters_done) *iters_done = it;
+    if (!conv) return fail(c, LBF_ENOTCONV, "steady adjoint not converged within max_iters");
     return LBF_OK;
 }
 

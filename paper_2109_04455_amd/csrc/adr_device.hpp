@@ -1,5 +1,13 @@
 // Per-node device code of the D2Q5 ADR step, shared by the single-lattice
 // kernels and the batched (many-instance) kernels.
+//
+// Populations are stored as Real (FP32 or FP64) and the arithmetic of a node
+// update runs in Acc.  With FP32 storage the default Acc is FP64: each stored
+// population is then rounded exactly once per step (at the store).  At a
+// steady state the FP32 fixed point differs from the exact one by the
+// per-step rounding residual times the residence time of the lattice, so
+// fewer and unbiased roundings matter; the kernel is bandwidth-bound and the
+// FP64 arithmetic costs no time.
 #pragma once
 
 #include "stencil.hpp"
@@ -11,137 +19,227 @@ namespace adr {
 enum { DE = 1, DN = 2, DW = 3, DS = 4 };
 constexpr unsigned BIT_E = 1u, BIT_N = 2u, BIT_W = 4u, BIT_S = 8u;
 
-template <typename Real>
-__device__ __forceinline__ Real w5(int i)
+template <typename T>
+__device__ __forceinline__ T w5(int i)
 {
-    return i == 0 ? Real(1) / Real(3) : Real(1) / Real(6);
+    return i == 0 ? T(1) / T(3) : T(1) / T(6);
 }
 
 // Gather the pre-collision (shifted) populations of one species at node
 // (x, y) from the post-collision lattice `src` (base of this species).
-template <typename Real, bool NT = false>
+template <typename Real, typename Acc, bool NT>
 __device__ __forceinline__ void pull5(const Real *__restrict__ src, size_t P, size_t id, int x,
-                                      int nx, int nxp, unsigned m, bool species_a, Real inlet_e,
-                                      Real (&h)[5])
+                                      int nx, int nxp, unsigned m, bool species_a, Acc inlet_e,
+                                      Acc (&h)[5])
 {
-    h[0] = ld<NT>(src + id);
+    h[0] = Acc(ld<NT>(src + id));
     // E arrives from x - 1
     if (x == 0)
-        h[DE] = species_a ? inlet_e - ld<NT>(src + DW * P + id) : ld<NT>(src + DW * P + id);
+        h[DE] = species_a ? inlet_e - Acc(ld<NT>(src + DW * P + id)) : Acc(ld<NT>(src + DW * P + id));
     else if (m & BIT_W)
-        h[DE] = ld<NT>(src + DW * P + id);
+        h[DE] = Acc(ld<NT>(src + DW * P + id));
     else
-        h[DE] = ld<NT>(src + DE * P + id - 1);
+        h[DE] = Acc(ld<NT>(src + DE * P + id - 1));
     // N arrives from y - 1
-    h[DN] = (m & BIT_S) ? ld<NT>(src + DS * P + id) : ld<NT>(src + DN * P + id - nxp);
+    h[DN] = Acc((m & BIT_S) ? ld<NT>(src + DS * P + id) : ld<NT>(src + DN * P + id - nxp));
     // W arrives from x + 1
     if (x == nx - 1) {
-        const Real sum = ld<NT>(src + id) + ld<NT>(src + DE * P + id) + ld<NT>(src + DN * P + id) +
-                         ld<NT>(src + DW * P + id) + ld<NT>(src + DS * P + id);
-        h[DW] = Real(2) * w5<Real>(DW) * sum - ld<NT>(src + DE * P + id);
+        const Acc sum = Acc(ld<NT>(src + id)) + Acc(ld<NT>(src + DE * P + id)) +
+                        Acc(ld<NT>(src + DN * P + id)) + Acc(ld<NT>(src + DW * P + id)) +
+                        Acc(ld<NT>(src + DS * P + id));
+        h[DW] = Acc(2) * w5<Acc>(DW) * sum - Acc(ld<NT>(src + DE * P + id));
     } else if (m & BIT_E) {
-        h[DW] = ld<NT>(src + DE * P + id);
+        h[DW] = Acc(ld<NT>(src + DE * P + id));
     } else {
-        h[DW] = ld<NT>(src + DW * P + id + 1);
+        h[DW] = Acc(ld<NT>(src + DW * P + id + 1));
     }
     // S arrives from y + 1
-    h[DS] = (m & BIT_N) ? ld<NT>(src + DN * P + id) : ld<NT>(src + DS * P + id + nxp);
+    h[DS] = Acc((m & BIT_N) ? ld<NT>(src + DN * P + id) : ld<NT>(src + DS * P + id + nxp));
+}
+
+// Gather for a box periodic in x and y (no inlet or outlet); solid
+// neighbours still bounce back.  nb[d] are the wrapped neighbour indices.
+template <typename Real, typename Acc, bool NT>
+__device__ __forceinline__ void pull5_periodic(const Real *__restrict__ src, size_t P, size_t id,
+                                               const size_t (&nb)[5], unsigned m, Acc (&h)[5])
+{
+    h[0] = Acc(ld<NT>(src + id));
+    h[DE] = Acc((m & BIT_W) ? ld<NT>(src + DW * P + id) : ld<NT>(src + DE * P + nb[DW]));
+    h[DN] = Acc((m & BIT_S) ? ld<NT>(src + DS * P + id) : ld<NT>(src + DN * P + nb[DS]));
+    h[DW] = Acc((m & BIT_E) ? ld<NT>(src + DE * P + id) : ld<NT>(src + DW * P + nb[DE]));
+    h[DS] = Acc((m & BIT_N) ? ld<NT>(src + DN * P + id) : ld<NT>(src + DS * P + nb[DN]));
+}
+
+// Neighbour indices x + c_d of node (x, y), wrapped in x and y.
+__device__ __forceinline__ void periodic_neighbours(int x, int y, int nx, int ny, int nxp,
+                                                    size_t (&nb)[5])
+{
+    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+    nb[0] = (size_t)y * nxp + x;
+    nb[DE] = (size_t)y * nxp + xp;
+    nb[DN] = (size_t)yp * nxp + x;
+    nb[DW] = (size_t)y * nxp + xm;
+    nb[DS] = (size_t)ym * nxp + x;
 }
 
 // BGK collision of one species in shifted form (cref = 0 for B and C).
-template <typename Real>
-__device__ __forceinline__ void collide5(Real (&h)[5], Real delta, Real cref, const Real (&p)[5],
-                                         Real omega)
+template <typename Acc>
+__device__ __forceinline__ void collide5(Acc (&h)[5], Acc delta, Acc cref, const Acc (&p)[5],
+                                         Acc omega)
 {
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-        const Real w = w5<Real>(i);
-        const Real target = w * p[i] * cref + w * (Real(1) + p[i]) * delta;
+        const Acc w = w5<Acc>(i);
+        const Acc target = w * p[i] * cref + w * (Acc(1) + p[i]) * delta;
         h[i] -= omega * (h[i] - target);
     }
 }
 
-template <typename Real>
-__device__ __forceinline__ void eq_factors(Real u, Real v, Real (&p)[5])
+template <typename Acc>
+__device__ __forceinline__ void eq_factors(Acc u, Acc v, Acc (&p)[5])
 {
-    const Real uu = Real(1.5) * (u * u + v * v);
+    const Acc uu = Acc(1.5) * (u * u + v * v);
     p[0] = -uu;
-    p[DE] = Real(3) * u + Real(4.5) * u * u - uu;
-    p[DN] = Real(3) * v + Real(4.5) * v * v - uu;
-    p[DW] = -Real(3) * u + Real(4.5) * u * u - uu;
-    p[DS] = -Real(3) * v + Real(4.5) * v * v - uu;
+    p[DE] = Acc(3) * u + Acc(4.5) * u * u - uu;
+    p[DN] = Acc(3) * v + Acc(4.5) * v * v - uu;
+    p[DW] = -Acc(3) * u + Acc(4.5) * u * u - uu;
+    p[DS] = -Acc(3) * v + Acc(4.5) * v * v - uu;
 }
 
 // Collide + react one node given its gathered populations (in place);
-// records (C_A, C_B) at trace nodes when TRACE.
-template <typename Real, int S, bool TRACE>
-__device__ __forceinline__ void collide_react(const AdrArgs<Real> &a, size_t id, unsigned m, Real u,
-                                              Real v, Real (&h)[S][5])
+// records (C_A, C_B) at trace nodes when TRACE.  MODE 0: link reaction, only
+// the population heading into a catalytic node reacts (rate of that node);
+// MODE 1: the paper's comparison variant, every population of a fluid node
+// next to catalysts reacts, with the mean rate of its catalytic neighbours of
+// each type.  nb: neighbour indices x + c_d (NULL: the unwrapped lattice).
+template <typename Real, typename Acc, int S, bool TRACE, int MODE = 0>
+__device__ __forceinline__ void collide_react(const AdrArgs<Real> &a, size_t id, unsigned m, Acc u,
+                                              Acc v, Acc (&h)[S][5], const size_t *nb = nullptr)
 {
-    Real p[5];
+    Acc p[5];
     eq_factors(u, v, p);
-    Real c[S];
+    Acc c[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        const Real delta = h[s][0] + h[s][1] + h[s][2] + h[s][3] + h[s][4];
-        const Real cref = s == 0 ? a.cref : Real(0);
+        const Acc delta = h[s][0] + h[s][1] + h[s][2] + h[s][3] + h[s][4];
+        const Acc cref = s == 0 ? Acc(a.cref) : Acc(0);
         c[s] = cref + delta;
-        collide5(h[s], delta, cref, p, a.omega);
+        collide5(h[s], delta, cref, p, Acc(a.omega));
     }
     if (m & 0xF0u) {
-        // link reaction (Eq. source_lbm): the population heading into a
-        // catalytic node loses k w_i C_src, the product gains it
         const int off[5] = {0, 1, a.nxp, -1, -a.nxp};
+        if (MODE == 0) {
+            // Eq. source_lbm at the links: the population heading into a
+            // catalytic node loses k w_i C_src, the product gains it
 #pragma unroll
-        for (int i = 1; i < 5; ++i) {
-            if (!((m >> (3 + i)) & 1u)) continue;
-            const size_t sid = id + off[i];
-            const Real k = a.kr[sid];
-            if (a.type[sid] == 2) {
-                const Real r = k * w5<Real>(i) * c[0];
-                h[0][i] -= r;
-                h[1][i] += r;
-            } else if (S == 3) {
-                const Real r = k * w5<Real>(i) * c[1];
-                h[1][i] -= r;
-                h[S - 1][i] += r;
+            for (int i = 1; i < 5; ++i) {
+                if (!((m >> (3 + i)) & 1u)) continue;
+                const size_t sid = nb ? nb[i] : id + off[i];
+                const Acc k = Acc(a.kr[sid]);
+                if (a.type[sid] == 2) {
+                    const Acc r = k * w5<Acc>(i) * c[0];
+                    h[0][i] -= r;
+                    h[1][i] += r;
+                } else if (S == 3) {
+                    const Acc r = k * w5<Acc>(i) * c[1];
+                    h[1][i] -= r;
+                    h[S - 1][i] += r;
+                }
+            }
+        } else {
+            Acc ks[2] = {0, 0};
+            int kc[2] = {0, 0};
+#pragma unroll
+            for (int i = 1; i < 5; ++i) {
+                if (!((m >> (3 + i)) & 1u)) continue;
+                const size_t sid = nb ? nb[i] : id + off[i];
+                const int q = a.type[sid] == 2 ? 0 : 1;
+                ks[q] += Acc(a.kr[sid]);
+                kc[q] += 1;
+            }
+#pragma unroll
+            for (int q = 0; q < 2 && q < S - 1; ++q) {
+                if (kc[q] == 0) continue;
+                const Acc kk = ks[q] / Acc(kc[q]);
+#pragma unroll
+                for (int j = 0; j < 5; ++j) {
+                    const Acc r = kk * w5<Acc>(j) * c[q];
+                    h[q][j] -= r;
+                    h[q + 1][j] += r;
+                }
             }
         }
         if (TRACE) {
             const int t = a.trace_idx[id];
-            a.trace[2 * t] = c[0];
-            a.trace[2 * t + 1] = S == 3 ? c[1] : Real(0);
+            a.trace[2 * t] = Real(c[0]);
+            a.trace[2 * t + 1] = S == 3 ? Real(c[1]) : Real(0);
         }
     }
 }
 
 // Collide + react + store for one node given its gathered populations.
-template <typename Real, int S, bool TRACE, bool NT = false>
+template <typename Real, typename Acc, int S, bool TRACE, bool NT>
 __device__ __forceinline__ void collide_react_store(const AdrArgs<Real> &a, size_t id, unsigned m,
-                                                    Real (&h)[S][5])
+                                                    Acc (&h)[S][5])
 {
     const size_t P = a.plane;
-    collide_react<Real, S, TRACE>(a, id, m, a.ua[id], a.ua[P + id], h);
+    collide_react<Real, Acc, S, TRACE>(a, id, m, Acc(a.ua[id]), Acc(a.ua[P + id]), h);
 #pragma unroll
     for (int s = 0; s < S; ++s)
 #pragma unroll
-        for (int i = 0; i < 5; ++i) st<NT>(a.dst + (s * 5 + i) * P + id, h[s][i]);
+        for (int i = 0; i < 5; ++i) st<NT>(a.dst + (s * 5 + i) * P + id, Real(h[s][i]));
 }
 
 // Full update of node (x, y): gather, collide, react, store.
-template <typename Real, int S, bool TRACE, bool NT>
+template <typename Real, typename Acc, int S, bool TRACE, bool NT>
 __device__ __forceinline__ void node_update(const AdrArgs<Real> &a, int x, int y)
 {
     const size_t id = (size_t)y * a.nxp + x;
     const unsigned m = a.mask5[id];
     if (m == MASK5_SOLID) return;
     const size_t P = a.plane;
-    const Real inlet_e = Real(2) * w5<Real>(DE) * (a.cin - a.cref);
-    Real h[S][5];
+    const Acc inlet_e = Acc(2) * w5<Acc>(DE) * (Acc(a.cin) - Acc(a.cref));
+    Acc h[S][5];
 #pragma unroll
     for (int s = 0; s < S; ++s)
-        pull5<Real, NT>(a.src + (size_t)s * 5 * P, P, id, x, a.nx, a.nxp, m, s == 0, inlet_e, h[s]);
-    collide_react_store<Real, S, TRACE, NT>(a, id, m, h);
+        pull5<Real, Acc, NT>(a.src + (size_t)s * 5 * P, P, id, x, a.nx, a.nxp, m, s == 0, inlet_e,
+                             h[s]);
+    collide_react_store<Real, Acc, S, TRACE, NT>(a, id, m, h);
+}
+
+// Node update for the reaction variant (MODE 1) and/or the periodic box,
+// arithmetic in FP64.
+template <typename Real, int S, bool NT, int MODE, bool PERIODIC>
+__device__ __forceinline__ void node_update_ext(const AdrArgs<Real> &a, int x, int y)
+{
+    const size_t id = (size_t)y * a.nxp + x;
+    const unsigned m = a.mask5[id];
+    if (m == MASK5_SOLID) return;
+    const size_t P = a.plane;
+    double h[S][5];
+    size_t nb[5];
+    if (PERIODIC) {
+        periodic_neighbours(x, y, a.nx, a.ny, a.nxp, nb);
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+            pull5_periodic<Real, double, NT>(a.src + (size_t)s * 5 * P, P, id, nb, m, h[s]);
+    } else {
+        const int off[5] = {0, 1, a.nxp, -1, -a.nxp};
+#pragma unroll
+        for (int d = 0; d < 5; ++d) nb[d] = id + off[d];
+        const double inlet_e = 2.0 * w5<double>(DE) * (a.cin - a.cref);
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+            pull5<Real, double, NT>(a.src + (size_t)s * 5 * P, P, id, x, a.nx, a.nxp, m, s == 0,
+                                    inlet_e, h[s]);
+    }
+    collide_react<Real, double, S, false, MODE>(a, id, m, double(a.ua[id]), double(a.ua[P + id]),
+                                                h, nb);
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) st<NT>(a.dst + (s * 5 + i) * P + id, Real(h[s][i]));
 }
 
 }  // namespace adr

@@ -34,7 +34,8 @@ lbf_status validate_params(const lbf_params *p, std::string &why)
     if ((size_t)p->nx * (size_t)p->ny > (size_t)1 << 32) { why = "lattice too large"; return LBF_EINVAL; }
     if (p->real_bytes != 4 && p->real_bytes != 8) { why = "real_bytes must be 4 or 8"; return LBF_EINVAL; }
     if (p->nspecies != 2 && p->nspecies != 3) { why = "nspecies must be 2 or 3"; return LBF_EINVAL; }
-    if (p->reaction_mode != 0) { why = "only reaction_mode 0 (link reactions) is implemented"; return LBF_EINVAL; }
+    if (p->reaction_mode != 0 && p->reaction_mode != 1) { why = "reaction_mode must be 0 or 1"; return LBF_EINVAL; }
+    if (p->boundary != 0 && p->boundary != 1) { why = "boundary must be 0 (channel) or 1 (periodic)"; return LBF_EINVAL; }
     if (!(p->tau_f > 0.5) || !std::isfinite(p->tau_f)) { why = "tau_f must be > 0.5"; return LBF_EINVAL; }
     if (!(p->tau_g > 0.5) || !std::isfinite(p->tau_g)) { why = "tau_g must be > 0.5"; return LBF_EINVAL; }
     if (!(std::fabs(p->u0) < 0.3)) { why = "|u0| must be < 0.3"; return LBF_EINVAL; }
@@ -46,7 +47,12 @@ lbf_status validate_params(const lbf_params *p, std::string &why)
         return LBF_EINVAL;
     }
     if (p->variant < 0 || p->variant > 2) { why = "variant must be 0, 1 or 2"; return LBF_EINVAL; }
-    const bool vec = p->variant == 2 || (p->variant == 0 && p->real_bytes == 8);
+    const bool ext = p->reaction_mode != 0 || p->boundary != 0;
+    if (ext && p->variant == 2) {
+        why = "the vector kernel covers link reactions in a channel only (variant 0 or 1)";
+        return LBF_EINVAL;
+    }
+    const bool vec = !ext && (p->variant == 2 || (p->variant == 0 && p->real_bytes == 8));
     const int tx = p->tile_x > 0 ? p->tile_x : (vec ? 64 : 256);
     const int ty = p->tile_y > 0 ? p->tile_y : (vec ? 4 : 1);
     const int maxb = vec ? 256 : 1024;
@@ -254,11 +260,12 @@ lbf_status lbf_create(const lbf_params *p, lbf_ctx *out)
     if (st != LBF_OK) return st;  // context still returned so lbf_last_error works
     c->p = *p;
     c->xf = p->flux_col == -1 ? p->nx - 3 : p->flux_col;
-    c->cref = p->real_bytes == 4 ? p->c_in : 0.0;
+    c->cref = (p->real_bytes == 4 && !(p->flags & 4)) ? p->c_in : 0.0;
     c->L = make_launch(p->nx, p->ny, 256, 1);
     c->L.xcd_remap = !(p->flags & 1);
     layout(c);
-    const bool vec = p->variant == 2 || (p->variant == 0 && p->real_bytes == 8);
+    const bool ext = p->reaction_mode != 0 || p->boundary != 0;
+    const bool vec = !ext && (p->variant == 2 || (p->variant == 0 && p->real_bytes == 8));
     if (vec) {
         const int V = 16 / p->real_bytes;
         c->Lv = make_launch(c->nxp / V, p->ny, p->tile_x > 0 ? p->tile_x : 64,
@@ -269,8 +276,18 @@ lbf_status lbf_create(const lbf_params *p, lbf_ctx *out)
                             p->tile_y > 0 ? p->tile_y : 1);
     }
     c->Lv.xcd_remap = !(p->flags & 1);
-    c->Lv.nontemporal = !(p->flags & 2);
-    c->L.nontemporal = c->Lv.nontemporal;
+    // Streaming (non-temporal) accesses pay off once the two ADR lattices no
+    // longer fit the last-level cache; below that, cached accesses let steps
+    // hit in it.
+    const size_t adr_state = 2 * (size_t)p->nspecies * 5 * p->real_bytes * c->plane;
+    bool nt = adr_state > NT_MIN_BYTES;
+    if (p->flags & 64) nt = true;
+    if (p->flags & 2) nt = false;
+    c->Lv.nontemporal = c->L.nontemporal = nt;
+    c->Lv.fp32_math = c->L.fp32_math = (p->flags & 16) != 0;
+    c->Lv.mode = c->L.mode = p->reaction_mode;
+    c->Lv.periodic = c->L.periodic = p->boundary == 1;
+    c->flow_fp32_math = (p->flags & (16 | 32)) != 0;
     c->valid = true;
     return LBF_OK;
 }
@@ -315,13 +332,15 @@ lbf_status lbf_set_geometry(lbf_ctx c, const uint8_t *type_dev)
     hipError_t e = hipMemcpyAsync(t.data(), type_dev, t.size(), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "copy node_type");
-    for (int x = 0; x < nx; ++x)
-        if (t[x] == 0 || t[(size_t)(ny - 1) * nx + x] == 0)
-            return fail(c, LBF_EINVAL, "rows 0 and ny-1 must be solid");
+    if (c->p.boundary == 0)
+        for (int x = 0; x < nx; ++x)
+            if (t[x] == 0 || t[(size_t)(ny - 1) * nx + x] == 0)
+                return fail(c, LBF_EINVAL, "rows 0 and ny-1 must be solid");
     for (uint8_t v : t)
         if (v > 3) return fail(c, LBF_EINVAL, "node_type values must be 0..3");
     e = launch_masks(type_dev, (uint8_t *)c->ptr(c->off.type), (uint8_t *)c->ptr(c->off.mask5),
-                     (uint16_t *)c->ptr(c->off.mask9), nx, ny, c->nxp, c->p.nspecies, c->stream);
+                     (uint16_t *)c->ptr(c->off.mask9), nx, ny, c->nxp, c->p.nspecies,
+                     c->p.boundary == 1, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "mask kernel");
     int *counter = (int *)c->ptr(c->off.counter);
     e = hipMemsetAsync(counter, 0, sizeof(int), c->stream);
@@ -373,6 +392,7 @@ lbf_status lbf_flow_init(lbf_ctx c)
 {
     lbf_status st = check_ready(c, true);
     if (st != LBF_OK) return st;
+    if (c->p.boundary != 0) return fail(c, LBF_EINVAL, "the flow solve needs a channel (boundary 0)");
     c->fpar = 0;
     hipError_t e = launch_flow_init(c->p.real_bytes, flow_args<float>(c, 1), flow_args<double>(c, 1),
                                     c->stream);
@@ -507,6 +527,8 @@ lbf_status lbf_adr_run(lbf_ctx c, long max_steps, int check_every, double tol, l
     if (st != LBF_OK) return st;
     if (!c->adr_ready) return fail(c, LBF_ESTATE, "call lbf_adr_init first");
     if (check_every < 1 || max_steps < 0) return fail(c, LBF_EINVAL, "bad step counts");
+    if (tol > 0 && c->p.boundary != 0)
+        return fail(c, LBF_EINVAL, "a periodic box has no outlet flux: use tol <= 0");
     long steps = 0;
     double prev = NAN;
     bool conv = false;
@@ -543,6 +565,7 @@ lbf_status lbf_efficiency(lbf_ctx c, double *eps, double *N, double *inflow)
 {
     lbf_status st = check_ready(c, true);
     if (st != LBF_OK) return st;
+    if (c->p.boundary != 0) return fail(c, LBF_EINVAL, "a periodic box has no outlet flux");
     double o[4];
     st = compute_fluxes(c, o);
     if (st != LBF_OK) return st;
@@ -566,6 +589,22 @@ lbf_status lbf_get_concentration(lbf_ctx c, int species, void *out)
                                         c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "concentration kernel");
     return LBF_OK;
+}
+
+lbf_status lbf_adr_totals(lbf_ctx c, double *totals)
+{
+    lbf_status st = check_ready(c, true);
+    if (st != LBF_OK) return st;
+    if (!totals) return fail(c, LBF_EINVAL, "NULL output");
+    if (c->adr_steps < 1) return fail(c, LBF_ESTATE, "no ADR step taken yet");
+    const int prev = c->gpar ^ 1;
+    constexpr int NB = 256;  // blocks; 3 x NB partials fit the workspace partial block
+    double *partial = (double *)c->ptr(c->off.partial);
+    double *obs = (double *)c->ptr(c->off.obs);
+    hipError_t e = launch_totals(c->p.real_bytes, c->p.nspecies, adr_args<float>(c, prev),
+                                 adr_args<double>(c, prev), partial, NB, obs, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "totals kernel");
+    return read_obs(c, totals, c->p.nspecies);
 }
 
 lbf_status lbf_adr_steps(lbf_ctx c, long *steps)

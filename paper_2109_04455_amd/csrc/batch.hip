@@ -42,23 +42,51 @@ __device__ __forceinline__ void chunk_of_block(int ntiles, int &t0, int &t1)
     t1 = (int)((long long)ntiles * (b + 1) / G);
 }
 
-template <typename Real, int S, bool NT>
+template <typename Real>
+__device__ __forceinline__ void swap_parity(AdrArgs<Real> &a, int parity)
+{
+    if (parity) {
+        const Real *tmp = a.src;
+        a.src = a.dst;
+        a.dst = const_cast<Real *>(tmp);
+    }
+}
+
+// PERSIST: a fixed grid walks contiguous chunks of the tile table (next tile
+// prefetched, the instance's argument block reused while the instance does
+// not change).  Otherwise one block per table slot; slots past the live
+// count exit at once.
+template <typename Real, int S, bool NT, bool PERSIST>
 __global__ __launch_bounds__(256) void k_batch_adr(const Inst<Real> *insts, const int4 *tiles,
                                                    const int *ntiles, int parity, int tx, int ty)
 {
+    const int lx = (int)threadIdx.x % tx, ly = (int)threadIdx.x / tx;
+    if (!PERSIST) {
+        if ((int)blockIdx.x >= *ntiles) return;
+        const int4 T = tiles[blockIdx.x];
+        AdrArgs<Real> a = insts[T.x].adr;
+        swap_parity(a, parity);
+        const int x = T.y * tx + lx, y = T.z * ty + ly;
+        if (x < a.nx && y < a.ny) adr::node_update<Real, double, S, false, NT>(a, x, y);
+        return;
+    }
     int t0, t1;
     chunk_of_block(*ntiles, t0, t1);
+    if (t0 >= t1) return;
+    int4 T = tiles[t0];
+    int cur = T.x;
+    AdrArgs<Real> a = insts[cur].adr;
+    swap_parity(a, parity);
     for (int t = t0; t < t1; ++t) {
-        const int4 T = tiles[t];
-        AdrArgs<Real> a = insts[T.x].adr;
-        if (parity) {
-            const Real *tmp = a.src;
-            a.src = a.dst;
-            a.dst = const_cast<Real *>(tmp);
+        const int4 Tn = t + 1 < t1 ? tiles[t + 1] : T;
+        if (T.x != cur) {
+            cur = T.x;
+            a = insts[cur].adr;
+            swap_parity(a, parity);
         }
-        const int x = T.y * tx + (int)threadIdx.x % tx;
-        const int y = T.z * ty + (int)threadIdx.x / tx;
-        if (x < a.nx && y < a.ny) adr::node_update<Real, S, false, NT>(a, x, y);
+        const int x = T.y * tx + lx, y = T.z * ty + ly;
+        if (x < a.nx && y < a.ny) adr::node_update<Real, double, S, false, NT>(a, x, y);
+        T = Tn;
     }
 }
 
@@ -78,7 +106,7 @@ __global__ __launch_bounds__(256) void k_batch_flow(const Inst<Real> *insts, con
         }
         const int x = T.y * tx + (int)threadIdx.x % tx;
         const int y = T.z * ty + (int)threadIdx.x / tx;
-        if (x < a.nx && y < a.ny) flow::node_update<Real, WRITE_U, NT>(a, x, y);
+        if (x < a.nx && y < a.ny) flow::node_update<Real, double, WRITE_U, NT>(a, x, y);
     }
 }
 
@@ -184,6 +212,8 @@ struct lbf_batch_s {
            off_uprevp = 0, total = 0;
     int max_tiles = 0;
     int tx = 256, ty = 1, grid = 2048;
+    bool persistent = true;
+    bool nontemporal = true;
     char *ws = nullptr;
     hipStream_t stream = nullptr, cap_stream = nullptr;
     std::string err;
@@ -269,10 +299,18 @@ void batch_launch(lbf_batch b, int kind, int parity, bool write_u, hipStream_t s
     const dim3 g(b->grid), blk(b->tx * b->ty);
     auto I = (const Inst<Real> *)(b->ws + b->off_inst);
     if (kind == KIND_ADR) {
-        if (b->p[0].nspecies == 2)
-            hipLaunchKernelGGL((k_batch_adr<Real, 2, NT>), g, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
-        else
-            hipLaunchKernelGGL((k_batch_adr<Real, 3, NT>), g, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
+        const dim3 ga(b->persistent ? b->grid : b->max_tiles);
+        if (b->p[0].nspecies == 2) {
+            if (b->persistent)
+                hipLaunchKernelGGL((k_batch_adr<Real, 2, NT, true>), ga, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
+            else
+                hipLaunchKernelGGL((k_batch_adr<Real, 2, NT, false>), ga, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
+        } else {
+            if (b->persistent)
+                hipLaunchKernelGGL((k_batch_adr<Real, 3, NT, true>), ga, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
+            else
+                hipLaunchKernelGGL((k_batch_adr<Real, 3, NT, false>), ga, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
+        }
     } else if (write_u) {
         hipLaunchKernelGGL((k_batch_flow<Real, true, NT>), g, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
     } else {
@@ -282,7 +320,7 @@ void batch_launch(lbf_batch b, int kind, int parity, bool write_u, hipStream_t s
 
 hipError_t enqueue_batch_step(lbf_batch b, int kind, int parity, bool write_u, hipStream_t s)
 {
-    const bool nt = !(b->p[0].flags & 2);
+    const bool nt = b->nontemporal;
     if (b->p[0].real_bytes == 4) {
         if (nt) batch_launch<float, true>(b, kind, parity, write_u, s);
         else batch_launch<float, false>(b, kind, parity, write_u, s);
@@ -377,19 +415,27 @@ lbf_status lbf_batch_create(int n, const lbf_params *params, lbf_batch *out)
         const lbf_params &pi = params[i];
         lbf_status st = validate_params(&pi, why);
         if (st != LBF_OK) return bfail(b, st, "instance " + std::to_string(i) + ": " + why);
+        if (pi.reaction_mode != 0 || pi.boundary != 0)
+            return bfail(b, LBF_EINVAL, "the batch runs link reactions in channels only");
         if (pi.real_bytes != p0.real_bytes || pi.nspecies != p0.nspecies || pi.tau_f != p0.tau_f ||
             pi.u0 != p0.u0 || pi.c_in != p0.c_in || pi.reaction_mode != p0.reaction_mode)
             return bfail(b, LBF_EINVAL, "instances must share real_bytes, nspecies, tau_f, u0, c_in");
         Ctx &c = b->ctx[i];
         c.p = pi;
         c.xf = pi.flux_col == -1 ? pi.nx - 3 : pi.flux_col;
-        c.cref = pi.real_bytes == 4 ? pi.c_in : 0.0;
+        c.cref = (pi.real_bytes == 4 && !(pi.flags & 4)) ? pi.c_in : 0.0;
         c.L = make_launch(pi.nx, pi.ny, pi.tile_x, pi.tile_y);
         layout(&c);
         c.valid = true;
     }
     b->tx = p0.tile_x > 0 ? p0.tile_x : 256;
     b->ty = p0.tile_y > 0 ? p0.tile_y : 1;
+    b->persistent = !(p0.flags & 8);
+    // streaming accesses once the instances' ADR lattices outgrow the cache
+    size_t adr_state = 0;
+    for (int i = 0; i < n; ++i)
+        adr_state += 2 * (size_t)p0.nspecies * 5 * p0.real_bytes * b->ctx[i].plane;
+    b->nontemporal = (adr_state > NT_MIN_BYTES || (p0.flags & 64)) && !(p0.flags & 2);
     if (b->tx * b->ty > 256 || (b->tx * b->ty) % 64)
         return bfail(b, LBF_EINVAL, "batched tiles: tile_x * tile_y must be a multiple of 64, <= 256");
     size_t off = 0;

@@ -19,6 +19,7 @@ struct lbf_ctx_s {
     double cref = 0;   // storage shift of species A
     lbf::Launch L;   // one node per thread
     lbf::Launch Lv;  // ADR step launch (vectorised or not, per params.variant)
+    bool flow_fp32_math = false;  // flow step computes in FP32 (FP32 storage)
 
     // workspace (caller-owned) and its layout
     struct Offsets {
@@ -54,6 +55,10 @@ using Ctx = lbf_ctx_s;
 
 enum { KIND_ADR = 0, KIND_FLOW = 1 };
 constexpr long GRAPH_MIN_STEPS = 8;
+// Above this size of the two ADR lattices the population accesses stream
+// (non-temporal) by default: the 256 MiB last-level cache no longer holds a
+// step's working set.
+constexpr size_t NT_MIN_BYTES = (size_t)192 << 20;
 
 lbf_status fail(Ctx *c, lbf_status s, const std::string &msg);
 lbf_status validate_params(const lbf_params *p, std::string &why);
@@ -83,9 +88,9 @@ inline AdrArgs<Real> adr_args(Ctx *c, int src_buf)
     a.ny = c->p.ny;
     a.nxp = c->nxp;
     a.plane = c->plane;
-    a.omega = Real(1.0 / c->p.tau_g);
-    a.cin = Real(c->p.c_in);
-    a.cref = Real(c->cref);
+    a.omega = 1.0 / c->p.tau_g;
+    a.cin = c->p.c_in;
+    a.cref = c->cref;
     a.L = c->L;
     return a;
 }
@@ -102,9 +107,10 @@ inline FlowArgs<Real> flow_args(Ctx *c, int src_buf)
     a.ny = c->p.ny;
     a.nxp = c->nxp;
     a.plane = c->plane;
-    a.omega = Real(1.0 / c->p.tau_f);
+    a.omega = 1.0 / c->p.tau_f;
     a.u0 = c->p.u0;
     a.L = c->L;
+    a.L.fp32_math = c->flow_fp32_math;
     return a;
 }
 

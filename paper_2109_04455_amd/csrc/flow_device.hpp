@@ -1,5 +1,6 @@
 // Per-node device code of the D2Q9 flow step, shared by the single-lattice
-// and the batched kernels.
+// and the batched kernels.  Populations are stored as Real; the node update
+// computes in Acc (FP64 by default, so FP32 storage rounds once per store).
 #pragma once
 
 #include "stencil.hpp"
@@ -26,12 +27,13 @@ __device__ __forceinline__ Real inlet_u(int y, int ny, double u0)
 }
 
 // Collide the shifted populations h in place; returns (u, v) and writes them.
+// f_eq - w = w (drho + rho (3 cu + 4.5 cu^2 - 1.5 u.u)): opposite directions
+// share the even part (drho + rho (4.5 cu^2 - 1.5 u.u)) and differ in the sign
+// of the odd part 3 rho cu, so each pair costs one evaluation.
 template <typename Real>
 __device__ __forceinline__ void collide(Real (&h)[9], Real omega, Real &u, Real &v)
 {
-    Real drho = 0;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) drho += h[i];
+    const Real drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
     const Real jx = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
     const Real jy = (h[2] - h[4]) + (h[5] - h[8]) + (h[6] - h[7]);
     const Real rho = Real(1) + drho;
@@ -39,58 +41,69 @@ __device__ __forceinline__ void collide(Real (&h)[9], Real omega, Real &u, Real 
     u = jx * inv;
     v = jy * inv;
     const Real uu = Real(1.5) * (u * u + v * v);
+    const Real r3 = Real(3) * rho;
+    const Real r45 = Real(4.5) * rho;
+    const Real base = drho - rho * uu;
+    Real eq[9];
+    eq[0] = wgt<Real>(0) * base;
+    // cu per pair (direction, opposite): (E, W) u; (N, S) v; (NE, SW) u + v; (NW, SE) v - u
+    const Real cu[4] = {u, v, u + v, v - u};
+    const int dir[4] = {1, 2, 5, 6}, opp[4] = {3, 4, 7, 8};
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const Real cu = Real(CX[i]) * u + Real(CY[i]) * v;
-        // f_eq - w = w (drho + rho (3 cu + 4.5 cu^2 - 1.5 u.u))
-        const Real heq = wgt<Real>(i) * (drho + rho * (Real(3) * cu + Real(4.5) * cu * cu - uu));
-        h[i] -= omega * (h[i] - heq);
+    for (int q = 0; q < 4; ++q) {
+        const Real w = wgt<Real>(dir[q]);
+        const Real even = base + r45 * cu[q] * cu[q];
+        const Real odd = r3 * cu[q];
+        eq[dir[q]] = w * (even + odd);
+        eq[opp[q]] = w * (even - odd);
     }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) h[i] -= omega * (h[i] - eq[i]);
 }
 
 // Full update of node (x, y): gather (bounce-back, Zou-He), collide, store.
-template <typename Real, bool WRITE_U, bool NT = false>
+template <typename Real, typename Acc, bool WRITE_U, bool NT>
 __device__ __forceinline__ void node_update(const FlowArgs<Real> &a, int x, int y)
 {
     const size_t id = (size_t)y * a.nxp + x;
     const unsigned m = a.mask9[id];
     if (m & MASK9_SOLID) return;
     const size_t P = a.plane;
-    Real h[9];
+    Acc h[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const int sx = x - CX[i];
         if (sx < 0 || sx >= a.nx) {
             h[i] = 0;  // open boundary: filled by Zou-He below
         } else if (i != 0 && ((m >> (OPP[i] - 1)) & 1u)) {
-            h[i] = ld<NT>(a.src + OPP[i] * P + id);  // half-way bounce-back
+            h[i] = Acc(ld<NT>(a.src + OPP[i] * P + id));  // half-way bounce-back
         } else {
-            h[i] = ld<NT>(a.src + i * P + id - CX[i] - (ptrdiff_t)CY[i] * a.nxp);
+            h[i] = Acc(ld<NT>(a.src + i * P + id - CX[i] - (ptrdiff_t)CY[i] * a.nxp));
         }
     }
     if (x == 0) {
         // Zou-He velocity inlet, u = (u_in(y), 0): unknown E, NE, SE.
         // In shifted form the known sum f0+fN+fS+2(fW+fNW+fSW) is 1 + sum h.
-        const Real ux = inlet_u<Real>(y, a.ny, a.u0);
-        const Real rho = (Real(1) + h[0] + h[2] + h[4] + Real(2) * (h[3] + h[6] + h[7])) / (Real(1) - ux);
-        h[1] = h[3] + Real(2) / Real(3) * rho * ux;
-        h[5] = h[7] - Real(0.5) * (h[2] - h[4]) + rho * ux / Real(6);
-        h[8] = h[6] + Real(0.5) * (h[2] - h[4]) + rho * ux / Real(6);
+        const Acc ux = inlet_u<Acc>(y, a.ny, a.u0);
+        const Acc rho = (Acc(1) + h[0] + h[2] + h[4] + Acc(2) * (h[3] + h[6] + h[7])) / (Acc(1) - ux);
+        h[1] = h[3] + Acc(2) / Acc(3) * rho * ux;
+        h[5] = h[7] - Acc(0.5) * (h[2] - h[4]) + rho * ux / Acc(6);
+        h[8] = h[6] + Acc(0.5) * (h[2] - h[4]) + rho * ux / Acc(6);
     } else if (x == a.nx - 1) {
         // Zou-He pressure outlet, rho = 1, u_y = 0: unknown W, NW, SW
-        const Real ux = h[0] + h[2] + h[4] + Real(2) * (h[1] + h[5] + h[8]);
-        h[3] = h[1] - Real(2) / Real(3) * ux;
-        h[6] = h[8] - Real(0.5) * (h[2] - h[4]) - ux / Real(6);
-        h[7] = h[5] + Real(0.5) * (h[2] - h[4]) - ux / Real(6);
+        const Acc ux = h[0] + h[2] + h[4] + Acc(2) * (h[1] + h[5] + h[8]);
+        h[3] = h[1] - Acc(2) / Acc(3) * ux;
+        h[6] = h[8] - Acc(0.5) * (h[2] - h[4]) - ux / Acc(6);
+        h[7] = h[5] + Acc(0.5) * (h[2] - h[4]) - ux / Acc(6);
     }
-    Real u, v;
-    collide(h, a.omega, u, v);
+    Acc u, v;
+    collide(h, Acc(a.omega), u, v);
     if (WRITE_U) {
-        a.u[id] = u;
-        a.u[P + id] = v;
+        a.u[id] = Real(u);
+        a.u[P + id] = Real(v);
     }
 #pragma unroll
-    for (int i = 0; i < 9; ++i) st<NT>(a.dst + i * P + id, h[i]);
+    for (int i = 0; i < 9; ++i) st<NT>(a.dst + i * P + id, Real(h[i]));
 }
 
 }  // namespace flow

@@ -49,7 +49,7 @@ __device__ __forceinline__ void vstore(Real *p, const Real (&o)[V])
 // populations pulled from x-1 (x+1) come from the aligned vector of the
 // node's own x range plus one scalar element just outside it.  Results are
 // identical to k_adr_step node by node.
-template <typename Real, int S, bool TRACE, int V, bool NT>
+template <typename Real, typename Acc, int S, bool TRACE, int V, bool NT>
 __global__ __launch_bounds__(256) void k_adr_step_vec(AdrArgs<Real> a)
 {
     int xv, y;
@@ -74,8 +74,8 @@ __global__ __launch_bounds__(256) void k_adr_step_vec(AdrArgs<Real> a)
     Real ux[V], uy[V];
     vload<Real, V>(a.ua + id0, ux);
     vload<Real, V>(a.ua + P + id0, uy);
-    const Real inlet_e = Real(2) * w5<Real>(DE) * (a.cin - a.cref);
-    Real h[S][5][V];
+    const Acc inlet_e = Acc(2) * w5<Acc>(DE) * (Acc(a.cin) - Acc(a.cref));
+    Acc h[S][5][V];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const Real *src = a.src + (size_t)s * 5 * P;
@@ -94,15 +94,15 @@ __global__ __launch_bounds__(256) void k_adr_step_vec(AdrArgs<Real> a)
             const int x = x0 + j;
             h[s][0][j] = own0[j];
             if (x == 0)
-                h[s][DE][j] = s == 0 ? inlet_e - ownW[j] : ownW[j];
+                h[s][DE][j] = s == 0 ? inlet_e - Acc(ownW[j]) : Acc(ownW[j]);
             else if (m[j] & BIT_W)
                 h[s][DE][j] = ownW[j];
             else
                 h[s][DE][j] = j == 0 ? eL : ownE[j - 1];
             h[s][DN][j] = (m[j] & BIT_S) ? ownS[j] : upN[j];
             if (x == a.nx - 1) {
-                const Real sum = own0[j] + ownE[j] + ownN[j] + ownW[j] + ownS[j];
-                h[s][DW][j] = Real(2) * w5<Real>(DW) * sum - ownE[j];
+                const Acc sum = Acc(own0[j]) + Acc(ownE[j]) + Acc(ownN[j]) + Acc(ownW[j]) + Acc(ownS[j]);
+                h[s][DW][j] = Acc(2) * w5<Acc>(DW) * sum - Acc(ownE[j]);
             } else if (m[j] & BIT_E) {
                 h[s][DW][j] = ownE[j];
             } else {
@@ -114,17 +114,17 @@ __global__ __launch_bounds__(256) void k_adr_step_vec(AdrArgs<Real> a)
     Real out[S][5][V];
 #pragma unroll
     for (int j = 0; j < V; ++j) {
-        Real hn[S][5];
+        Acc hn[S][5];
 #pragma unroll
         for (int s = 0; s < S; ++s)
 #pragma unroll
             for (int i = 0; i < 5; ++i) hn[s][i] = h[s][i][j];
         const bool fl = m[j] != MASK5_SOLID;
-        if (fl) collide_react<Real, S, TRACE>(a, id0 + j, m[j], ux[j], uy[j], hn);
+        if (fl) collide_react<Real, Acc, S, TRACE>(a, id0 + j, m[j], Acc(ux[j]), Acc(uy[j]), hn);
 #pragma unroll
         for (int s = 0; s < S; ++s)
 #pragma unroll
-            for (int i = 0; i < 5; ++i) out[s][i][j] = fl ? hn[s][i] : Real(0);
+            for (int i = 0; i < 5; ++i) out[s][i][j] = fl ? Real(hn[s][i]) : Real(0);
     }
 #pragma unroll
     for (int s = 0; s < S; ++s)
@@ -132,13 +132,23 @@ __global__ __launch_bounds__(256) void k_adr_step_vec(AdrArgs<Real> a)
         for (int i = 0; i < 5; ++i) vstore<Real, V, NT>(a.dst + (s * 5 + i) * P + id0, out[s][i]);
 }
 
-template <typename Real, int S, bool TRACE, bool NT>
+template <typename Real, typename Acc, int S, bool TRACE, bool NT>
 __global__ __launch_bounds__(1024) void k_adr_step(AdrArgs<Real> a)
 {
     int x, y;
     tile_coords(a.L, x, y);
     if (x >= a.nx || y >= a.ny) return;
-    adr::node_update<Real, S, TRACE, NT>(a, x, y);
+    adr::node_update<Real, Acc, S, TRACE, NT>(a, x, y);
+}
+
+// Reaction variant and/or periodic box (FP64 arithmetic, no trace).
+template <typename Real, int S, bool NT, int MODE, bool PERIODIC>
+__global__ __launch_bounds__(1024) void k_adr_step_ext(AdrArgs<Real> a)
+{
+    int x, y;
+    tile_coords(a.L, x, y);
+    if (x >= a.nx || y >= a.ny) return;
+    adr::node_update_ext<Real, S, NT, MODE, PERIODIC>(a, x, y);
 }
 
 // Initial state: A at equilibrium with C = c_in and the ADR velocity, B = C = 0,
@@ -159,17 +169,34 @@ __global__ __launch_bounds__(1024) void k_adr_init(AdrArgs<Real> a)
             for (int i = 0; i < 5; ++i) a.dst[(s * 5 + i) * P + id] = 0;
         return;
     }
-    Real p[5];
-    eq_factors(a.ua[id], a.ua[P + id], p);
-    Real h[S][5];
+    double p[5];
+    eq_factors(double(a.ua[id]), double(a.ua[P + id]), p);
+    double h[S][5];
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
         // g_A = w_i c_in (1 + p_i), stored as g_A - w_i cref
-        h[0][i] = w5<Real>(i) * (a.cin * p[i] + (a.cin - a.cref));
+        h[0][i] = w5<double>(i) * (a.cin * p[i] + (a.cin - a.cref));
 #pragma unroll
         for (int s = 1; s < S; ++s) h[s][i] = 0;
     }
-    collide_react_store<Real, S, false>(a, id, m, h);
+    // first collision with the lattice's reaction rule and neighbour indices
+    size_t nb[5];
+    if (a.L.periodic) {
+        periodic_neighbours(x, y, a.nx, a.ny, a.nxp, nb);
+    } else {
+        const int off[5] = {0, 1, a.nxp, -1, -a.nxp};
+#pragma unroll
+        for (int d = 0; d < 5; ++d) nb[d] = id + off[d];
+    }
+    const double u = double(a.ua[id]), v = double(a.ua[P + id]);
+    if (a.L.mode == 1)
+        collide_react<Real, double, S, false, 1>(a, id, m, u, v, h, nb);
+    else
+        collide_react<Real, double, S, false, 0>(a, id, m, u, v, h, nb);
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) a.dst[(s * 5 + i) * P + id] = Real(h[s][i]);
 }
 
 // Concentration of one species after the last step: gather from the
@@ -182,15 +209,22 @@ __global__ __launch_bounds__(1024) void k_concentration(AdrArgs<Real> a, int spe
     if (x >= a.nx || y >= a.ny) return;
     const size_t id = (size_t)y * a.nxp + x;
     const unsigned m = a.mask5[id];
-    Real c = 0;
+    double c = 0;
     if (m != MASK5_SOLID) {
-        Real h[5];
-        const Real inlet_e = Real(2) * w5<Real>(DE) * (a.cin - a.cref);
-        pull5(a.src + (size_t)species * 5 * a.plane, a.plane, id, x, a.nx, a.nxp, m, species == 0,
-              inlet_e, h);
-        c = (species == 0 ? a.cref : Real(0)) + (h[0] + h[1] + h[2] + h[3] + h[4]);
+        double h[5];
+        const double inlet_e = 2.0 * w5<double>(DE) * (a.cin - a.cref);
+        if (a.L.periodic) {
+            size_t nb[5];
+            periodic_neighbours(x, y, a.nx, a.ny, a.nxp, nb);
+            pull5_periodic<Real, double, false>(a.src + (size_t)species * 5 * a.plane, a.plane, id,
+                                                nb, m, h);
+        } else {
+            pull5<Real, double, false>(a.src + (size_t)species * 5 * a.plane, a.plane, id, x, a.nx,
+                                       a.nxp, m, species == 0, inlet_e, h);
+        }
+        c = (species == 0 ? a.cref : 0.0) + (h[0] + h[1] + h[2] + h[3] + h[4]);
     }
-    out[(size_t)y * a.nx + x] = c;
+    out[(size_t)y * a.nx + x] = Real(c);
 }
 
 // Concentrations (C_A, C_B) at the trace nodes after the last step.
@@ -202,16 +236,79 @@ __global__ __launch_bounds__(256) void k_trace_conc(AdrArgs<Real> a, const int32
     const size_t id = nodes[t];
     const int x = (int)(id % a.nxp);
     const unsigned m = a.mask5[id];
-    const Real inlet_e = Real(2) * w5<Real>(DE) * (a.cin - a.cref);
-    Real h[5];
-    pull5(a.src, a.plane, id, x, a.nx, a.nxp, m, true, inlet_e, h);
-    a.trace[2 * t] = a.cref + (h[0] + h[1] + h[2] + h[3] + h[4]);
-    Real cb = 0;
+    const double inlet_e = 2.0 * w5<double>(DE) * (a.cin - a.cref);
+    double h[5];
+    pull5<Real, double, false>(a.src, a.plane, id, x, a.nx, a.nxp, m, true, inlet_e, h);
+    a.trace[2 * t] = Real(a.cref + (h[0] + h[1] + h[2] + h[3] + h[4]));
+    double cb = 0;
     if (S == 3) {
-        pull5(a.src + 5 * a.plane, a.plane, id, x, a.nx, a.nxp, m, false, inlet_e, h);
+        pull5<Real, double, false>(a.src + 5 * a.plane, a.plane, id, x, a.nx, a.nxp, m, false,
+                                   inlet_e, h);
         cb = h[0] + h[1] + h[2] + h[3] + h[4];
     }
-    a.trace[2 * t + 1] = cb;
+    a.trace[2 * t + 1] = Real(cb);
+}
+
+// Total amount of every species after the last step (FP64 sums over the
+// fluid nodes; per-block partials, then one block in fixed order).
+template <typename Real, int S>
+__global__ __launch_bounds__(256) void k_totals(AdrArgs<Real> a, double *partial)
+{
+    __shared__ double sm[S][256];
+    double acc[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc[s] = 0.0;
+    const size_t n = (size_t)a.nx * a.ny;
+    const double inlet_e = 2.0 * w5<double>(DE) * (a.cin - a.cref);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % a.nx), y = (int)(i / a.nx);
+        const size_t id = (size_t)y * a.nxp + x;
+        const unsigned m = a.mask5[id];
+        if (m == MASK5_SOLID) continue;
+        size_t nb[5];
+        if (a.L.periodic) periodic_neighbours(x, y, a.nx, a.ny, a.nxp, nb);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            double h[5];
+            if (a.L.periodic)
+                pull5_periodic<Real, double, false>(a.src + (size_t)s * 5 * a.plane, a.plane, id, nb, m, h);
+            else
+                pull5<Real, double, false>(a.src + (size_t)s * 5 * a.plane, a.plane, id, x, a.nx,
+                                           a.nxp, m, s == 0, inlet_e, h);
+            acc[s] += (s == 0 ? a.cref : 0.0) + (h[0] + h[1] + h[2] + h[3] + h[4]);
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) sm[s][threadIdx.x] = acc[s];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st)
+#pragma unroll
+            for (int s = 0; s < S; ++s) sm[s][threadIdx.x] += sm[s][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int s = 0; s < S; ++s) partial[(size_t)s * gridDim.x + blockIdx.x] = sm[s][0];
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials(const double *partial, int nblocks, int ns,
+                                                      double *out)
+{
+    __shared__ double sm[256];
+    for (int s = 0; s < ns; ++s) {
+        double acc = 0.0;
+        for (int i = threadIdx.x; i < nblocks; i += blockDim.x) acc += partial[(size_t)s * nblocks + i];
+        sm[threadIdx.x] = acc;
+        __syncthreads();
+        for (int st = 128; st > 0; st >>= 1) {
+            if (threadIdx.x < st) sm[threadIdx.x] += sm[threadIdx.x + st];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[s] = sm[0];
+        __syncthreads();
+    }
 }
 
 // Outlet fluxes and inlet flux of the last streaming, from the previous
@@ -276,30 +373,64 @@ __global__ void k_pad(const Real *src, Real *dst, int nx, int ny, int nxp)
     }
 }
 
-template <typename Real, int S, bool TRACE, bool NT>
+template <typename Real, typename Acc, int S, bool TRACE, bool NT>
 void step_launch(const AdrArgs<Real> &a, hipStream_t s)
 {
     constexpr int V = 16 / sizeof(Real);
     if (a.L.vec)
-        hipLaunchKernelGGL((k_adr_step_vec<Real, S, TRACE, V, NT>), a.L.grid(), a.L.block(), 0, s, a);
+        hipLaunchKernelGGL((k_adr_step_vec<Real, Acc, S, TRACE, V, NT>), a.L.grid(), a.L.block(), 0,
+                           s, a);
     else
-        hipLaunchKernelGGL((k_adr_step<Real, S, TRACE, NT>), a.L.grid(), a.L.block(), 0, s, a);
+        hipLaunchKernelGGL((k_adr_step<Real, Acc, S, TRACE, NT>), a.L.grid(), a.L.block(), 0, s, a);
+}
+
+template <typename Real, typename Acc, int S>
+void step_launch_nt(bool trace, bool nt, const AdrArgs<Real> &a, hipStream_t s)
+{
+    if (trace)
+        nt ? step_launch<Real, Acc, S, true, true>(a, s) : step_launch<Real, Acc, S, true, false>(a, s);
+    else
+        nt ? step_launch<Real, Acc, S, false, true>(a, s) : step_launch<Real, Acc, S, false, false>(a, s);
+}
+
+// FP64 storage always computes in FP64; FP32 storage computes in FP64 unless
+// the launch asks for FP32 arithmetic.
+template <typename Real, int S, bool NT>
+void ext_launch(const AdrArgs<Real> &a, hipStream_t s)
+{
+    const dim3 g = a.L.grid(), b = a.L.block();
+    if (a.L.mode == 1) {
+        if (a.L.periodic)
+            hipLaunchKernelGGL((k_adr_step_ext<Real, S, NT, 1, true>), g, b, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_adr_step_ext<Real, S, NT, 1, false>), g, b, 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_adr_step_ext<Real, S, NT, 0, true>), g, b, 0, s, a);
+    }
 }
 
 template <typename Real>
 hipError_t step_dispatch(int ns, bool trace, const AdrArgs<Real> &a, hipStream_t s)
 {
     const bool nt = a.L.nontemporal;
+    if (a.L.mode != 0 || a.L.periodic) {
+        if (ns == 2)
+            nt ? ext_launch<Real, 2, true>(a, s) : ext_launch<Real, 2, false>(a, s);
+        else
+            nt ? ext_launch<Real, 3, true>(a, s) : ext_launch<Real, 3, false>(a, s);
+        return hipGetLastError();
+    }
+    const bool f32math = sizeof(Real) == 4 && a.L.fp32_math;
     if (ns == 2) {
-        if (trace)
-            nt ? step_launch<Real, 2, true, true>(a, s) : step_launch<Real, 2, true, false>(a, s);
+        if (f32math)
+            step_launch_nt<Real, float, 2>(trace, nt, a, s);
         else
-            nt ? step_launch<Real, 2, false, true>(a, s) : step_launch<Real, 2, false, false>(a, s);
+            step_launch_nt<Real, double, 2>(trace, nt, a, s);
     } else {
-        if (trace)
-            nt ? step_launch<Real, 3, true, true>(a, s) : step_launch<Real, 3, true, false>(a, s);
+        if (f32math)
+            step_launch_nt<Real, float, 3>(trace, nt, a, s);
         else
-            nt ? step_launch<Real, 3, false, true>(a, s) : step_launch<Real, 3, false, false>(a, s);
+            step_launch_nt<Real, double, 3>(trace, nt, a, s);
     }
     return hipGetLastError();
 }
@@ -326,6 +457,21 @@ hipError_t launch_adr_init(int real_bytes, int ns, const AdrArgs<float> &af,
         else
             hipLaunchKernelGGL((k_adr_init<double, 3>), ad.L.grid(), ad.L.block(), 0, s, ad);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_totals(int real_bytes, int ns, const AdrArgs<float> &af, const AdrArgs<double> &ad,
+                         double *partial, int nblocks, double *out, hipStream_t s)
+{
+    const dim3 g(nblocks), b(256);
+    if (real_bytes == 4) {
+        if (ns == 2) hipLaunchKernelGGL((k_totals<float, 2>), g, b, 0, s, af, partial);
+        else hipLaunchKernelGGL((k_totals<float, 3>), g, b, 0, s, af, partial);
+    } else {
+        if (ns == 2) hipLaunchKernelGGL((k_totals<double, 2>), g, b, 0, s, ad, partial);
+        else hipLaunchKernelGGL((k_totals<double, 3>), g, b, 0, s, ad, partial);
+    }
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partial, nblocks, ns, out);
     return hipGetLastError();
 }
 

@@ -19,30 +19,39 @@ namespace {
 
 using namespace flow;
 
-template <typename Real, bool WRITE_U, bool NT>
+template <typename Real, typename Acc, bool WRITE_U, bool NT>
 __global__ __launch_bounds__(1024) void k_flow_step(FlowArgs<Real> a)
 {
     int x, y;
     tile_coords(a.L, x, y);
     if (x >= a.nx || y >= a.ny) return;
-    flow::node_update<Real, WRITE_U, NT>(a, x, y);
+    flow::node_update<Real, Acc, WRITE_U, NT>(a, x, y);
+}
+
+template <typename Real, typename Acc>
+void flow_launch_acc(bool write_u, const FlowArgs<Real> &a, hipStream_t s)
+{
+    const dim3 g = a.L.grid(), b = a.L.block();
+    if (a.L.nontemporal) {
+        if (write_u)
+            hipLaunchKernelGGL((k_flow_step<Real, Acc, true, true>), g, b, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_flow_step<Real, Acc, false, true>), g, b, 0, s, a);
+    } else {
+        if (write_u)
+            hipLaunchKernelGGL((k_flow_step<Real, Acc, true, false>), g, b, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_flow_step<Real, Acc, false, false>), g, b, 0, s, a);
+    }
 }
 
 template <typename Real>
 void flow_launch(bool write_u, const FlowArgs<Real> &a, hipStream_t s)
 {
-    const dim3 g = a.L.grid(), b = a.L.block();
-    if (a.L.nontemporal) {
-        if (write_u)
-            hipLaunchKernelGGL((k_flow_step<Real, true, true>), g, b, 0, s, a);
-        else
-            hipLaunchKernelGGL((k_flow_step<Real, false, true>), g, b, 0, s, a);
-    } else {
-        if (write_u)
-            hipLaunchKernelGGL((k_flow_step<Real, true, false>), g, b, 0, s, a);
-        else
-            hipLaunchKernelGGL((k_flow_step<Real, false, false>), g, b, 0, s, a);
-    }
+    if (sizeof(Real) == 4 && a.L.fp32_math)
+        flow_launch_acc<Real, float>(write_u, a, s);
+    else
+        flow_launch_acc<Real, double>(write_u, a, s);
 }
 
 // Initial state f = f_eq(1, (u_in(y), 0)), then one collision (the stored
@@ -63,19 +72,19 @@ __global__ __launch_bounds__(1024) void k_flow_init(FlowArgs<Real> a)
         for (int i = 0; i < 9; ++i) a.dst[i * P + id] = 0;
         return;
     }
-    const Real ux = inlet_u<Real>(y, a.ny, a.u0);
-    Real h[9];
+    const double ux = inlet_u<double>(y, a.ny, a.u0);
+    double h[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        const Real cu = Real(CX[i]) * ux;
-        h[i] = wgt<Real>(i) * (Real(3) * cu + Real(4.5) * cu * cu - Real(1.5) * ux * ux);
+        const double cu = double(CX[i]) * ux;
+        h[i] = wgt<double>(i) * (3.0 * cu + 4.5 * cu * cu - 1.5 * ux * ux);
     }
-    Real u, v;
+    double u, v;
     collide(h, a.omega, u, v);
-    a.u[id] = u;
-    a.u[P + id] = v;
+    a.u[id] = Real(u);
+    a.u[P + id] = Real(v);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) a.dst[i * P + id] = h[i];
+    for (int i = 0; i < 9; ++i) a.dst[i * P + id] = Real(h[i]);
 }
 
 // max |u - u_prev| over fluid nodes (both components); copies u -> u_prev.
@@ -151,6 +160,12 @@ hipError_t launch_du_max(int real_bytes, const void *u, void *uprev, const uint1
         hipLaunchKernelGGL(k_du_max<double>, dim3(nblocks), dim3(256), 0, s, (const double *)u,
                            (double *)uprev, mask9, plane, partial);
     hipLaunchKernelGGL(k_max_partials, dim3(1), dim3(256), 0, s, partial, nblocks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_du_max_partials(const double *partial, int n, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_max_partials, dim3(1), dim3(256), 0, s, partial, n, out);
     return hipGetLastError();
 }
 

@@ -12,8 +12,9 @@ constexpr int CY9[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 // catalytic neighbours along E, N, W, S) and the D2Q9 mask (solid
 // neighbours along the 8 moving directions).  Neighbours outside the
 // channel in y count as solid; outside in x they are the open inlet/outlet.
+// A periodic box wraps both directions.
 __global__ void k_masks(const uint8_t *type_in, uint8_t *type_pad, uint8_t *mask5, uint16_t *mask9,
-                        int nx, int ny, int nxp, int nspecies)
+                        int nx, int ny, int nxp, int nspecies, bool periodic)
 {
     const size_t n = (size_t)nxp * ny;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -34,7 +35,11 @@ __global__ void k_masks(const uint8_t *type_in, uint8_t *type_pad, uint8_t *mask
         }
         unsigned m9 = 0, m5 = 0;
         for (int d = 1; d < 9; ++d) {
-            const int sx = x + CX9[d], sy = y + CY9[d];
+            int sx = x + CX9[d], sy = y + CY9[d];
+            if (periodic) {
+                sx = (sx + nx) % nx;
+                sy = (sy + ny) % ny;
+            }
             bool solid, cat = false;
             if (sy < 0 || sy >= ny) {
                 solid = true;
@@ -104,10 +109,10 @@ __global__ void k_copy_bytes(const uint8_t *src, uint8_t *dst, size_t n)
 }  // namespace
 
 hipError_t launch_masks(const uint8_t *type_in, uint8_t *type_pad, uint8_t *mask5, uint16_t *mask9,
-                        int nx, int ny, int nxp, int nspecies, hipStream_t s)
+                        int nx, int ny, int nxp, int nspecies, bool periodic, hipStream_t s)
 {
     hipLaunchKernelGGL(k_masks, dim3(2048), dim3(256), 0, s, type_in, type_pad, mask5, mask9, nx, ny,
-                       nxp, nspecies);
+                       nxp, nspecies, periodic);
     return hipGetLastError();
 }
 

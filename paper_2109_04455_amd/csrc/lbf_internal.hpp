@@ -43,6 +43,9 @@ struct Launch {
     bool xcd_remap = true;
     bool vec = false;  // ADR step: V nodes per thread (tile covers tx*V nodes in x)
     bool nontemporal = false;  // streaming loads/stores for the populations
+    bool fp32_math = false;    // FP32 storage: compute in FP32 instead of FP64
+    int mode = 0;              // ADR reaction: 0 links, 1 all populations next to catalysts
+    bool periodic = false;     // ADR lattice periodic in x and y (no inlet / outlet)
     dim3 grid() const { return dim3(gx * gy, 1, 1); }
     dim3 block() const { return dim3(tx * ty, 1, 1); }
 };
@@ -55,7 +58,7 @@ struct FlowArgs {
     Real *u;            // [2][plane] velocity output (only when written)
     int nx, ny, nxp;
     size_t plane;
-    Real omega;         // 1 / tau_f
+    double omega;       // 1 / tau_f
     double u0;
     Launch L;
 };
@@ -72,9 +75,9 @@ struct AdrArgs {
     Real *trace;        // [ntrace][2] concentrations (C_A, C_B) of this step
     int nx, ny, nxp;
     size_t plane;
-    Real omega;         // 1 / tau_g
-    Real cin;           // inlet concentration of A
-    Real cref;          // storage shift of species A (populations stored as g - w_i cref)
+    double omega;       // 1 / tau_g
+    double cin;         // inlet concentration of A
+    double cref;        // storage shift of species A (populations stored as g - w_i cref)
     Launch L;
 };
 
@@ -82,7 +85,9 @@ struct AdrArgs {
 
 // launchers (return hipError_t of the launch)
 hipError_t launch_masks(const uint8_t *type_in, uint8_t *type_pad, uint8_t *mask5, uint16_t *mask9,
-                        int nx, int ny, int nxp, int nspecies, hipStream_t s);
+                        int nx, int ny, int nxp, int nspecies, bool periodic, hipStream_t s);
+hipError_t launch_totals(int real_bytes, int ns, const AdrArgs<float> &af, const AdrArgs<double> &ad,
+                         double *partial, int nblocks, double *out, hipStream_t s);
 hipError_t launch_trace_list(const uint8_t *mask5, int32_t *trace_idx, int32_t *trace_nodes,
                              int *counter, int nx, int ny, int nxp, hipStream_t s);
 hipError_t launch_copy_rates(const double *k_in, const uint8_t *type_pad, void *kr, int real_bytes,
@@ -95,6 +100,7 @@ hipError_t launch_flow_step(int real_bytes, bool write_u, const FlowArgs<float> 
 hipError_t launch_du_max(int real_bytes, const void *u, void *uprev, const uint16_t *mask9,
                          size_t n2, double *partial, int nblocks, double *out, hipStream_t s);
 
+hipError_t launch_du_max_partials(const double *partial, int n, double *out, hipStream_t s);
 hipError_t launch_velocity_handoff(int real_bytes, const void *u, void *ua, const uint8_t *mask5,
                                    double vel_scale, size_t plane, hipStream_t s);
 hipError_t launch_adr_init(int real_bytes, int ns, const AdrArgs<float> &af,

@@ -60,7 +60,8 @@ def _create(L, p):
 
 @pytest.mark.parametrize("field,value,needle", [
     ("nx", 4, "nx >= 8"), ("ny", 2, "ny >= 3"), ("real_bytes", 2, "real_bytes"),
-    ("nspecies", 4, "nspecies"), ("reaction_mode", 1, "reaction_mode"),
+    ("nspecies", 4, "nspecies"), ("reaction_mode", 2, "reaction_mode"),
+    ("boundary", 2, "boundary"),
     ("tau_f", 0.5, "tau_f"), ("tau_g", 0.4, "tau_g"), ("u0", 0.4, "u0"),
     ("vel_scale", -1.0, "vel_scale"), ("flux_col", 63, "flux_col"), ("tile_x", 1000, "tile_x"), ("tile_y", 20, "tile_x"),
 ])
@@ -86,6 +87,18 @@ def test_valid_parameters_and_workspace_arithmetic(L):
     assert L.lbf_flow_init(h) == -6
     assert L.lbf_bind(h, None, 0, None) == -1
     L.lbf_destroy(h)
+
+
+@pytest.mark.parametrize("kw", [dict(reaction_mode=1, variant=2), dict(boundary=1, variant=2)])
+def test_vector_kernel_rejects_reaction_variant_and_periodic_box(L, kw):
+    st, msg = _create(L, _params(L, **kw))
+    assert st == -1 and "vector" in msg
+
+
+def test_reaction_variant_and_periodic_box_accepted(L):
+    for kw in (dict(reaction_mode=1), dict(boundary=1), dict(reaction_mode=1, boundary=1, real_bytes=8)):
+        st, msg = _create(L, _params(L, **kw))
+        assert st == 0, msg
 
 
 def test_status_strings(L):

@@ -114,3 +114,24 @@ def test_adjoint_finite_differences_c1_geometry():
     scale = np.abs(fd).max()
     assert scale > 0 and eps0 > 0
     assert np.abs(ad - fd).max() <= 1e-3 * scale, (ad, fd)
+
+
+@pytest.mark.parametrize("real,tol", [("f64", 1e-8), ("f32", 2e-3)])
+def test_steady_adjoint_matches_direct_steady_adjoint(real, tol):
+    # iterate the adjoint at the converged state (no checkpoints) against the
+    # sparse direct solve of the steady adjoint
+    w = make_workload("tiny")
+    ux, uy, _, _ = R.flow_steady(w.node_type, w.tau_f, w.u0, 3000, tol=0)
+    grad_ss, eps_ss = System(w.node_type, w.k, ux, uy, 3, w.tau_g).steady_gradient()
+    c = _ctx(w, real)
+    c.flow_init()
+    c.flow_run(3000)
+    c.adr_init()
+    c.adr_run(40000, tol=0)
+    eps, grad, iters = c.adjoint_steady(max_iters=200000, check_every=500,
+                                        tol=1e-14 if real == "f64" else 1e-7)
+    grad = grad.cpu().numpy()
+    assert 0 < iters < 200000
+    assert abs(eps / eps_ss - 1) < tol
+    assert np.abs(grad - grad_ss).max() <= tol * np.abs(grad_ss).max()
+    assert (grad[w.node_type < 2] == 0).all()

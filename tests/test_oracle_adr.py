@@ -287,3 +287,77 @@ def test_direct_steady_gradient_matches_finite_differences(tiny_flow):
             e.append(System(w.node_type, kk, ux, uy, 3, w.tau_g).steady()[2])
         fd = (e[0] - e[1]) / (2 * h)
         assert abs(grad[y, x] - fd) < 1e-7 * abs(fd)
+
+
+# ------------------------- the paper's "all populations react" comparison variant
+def _closed_box_disc(kind=CAT1, k=0.3):
+    nx, ny = 40, 30
+    t = np.zeros((ny, nx), np.uint8)
+    owner = rasterize(t, [(20, 15)], 5)
+    surf = classify_surface(t, owner)
+    t[surf] = kind
+    return t, np.where(surf, k, 0.0), surf
+
+
+def test_all_populations_variant_first_step_removal():
+    # every fluid node next to a type-1 catalyst loses k c_in of A in one step
+    # (all five populations react, sum of w_i = 1), whatever its number of
+    # catalytic links -- against link mode, which removes k w_i c_in per link
+    t, k, surf = _closed_box_disc()
+    ny, nx = t.shape
+    reactive = 0
+    links = 0
+    for y in range(ny):
+        for x in range(nx):
+            if t[y, x] != 0:
+                continue
+            n = sum(t[(y + CY[i]) % ny, (x + CX[i]) % nx] == CAT1 for i in range(1, 5))
+            reactive += n > 0
+            links += n
+    z = np.zeros((ny, nx))
+    out = {}
+    for mode in (R.LINK, R.NODE_AT_CATALYST):
+        g = np.zeros((2, 5, ny, nx))
+        g[0] = np.where(t == 0, _eq_state(np.ones((ny, nx)), 0, 0)[0], 0.0)
+        a0 = g[0].sum()
+        R.adr_run(t, k, z, z, g, 0.9, 1, mode=mode, bc=R.PERIODIC_X | R.PERIODIC_Y)
+        out[mode] = a0 - g[0].sum()
+        assert abs(g[1].sum() - out[mode]) < 1e-12
+    assert abs(out[R.NODE_AT_CATALYST] - 0.3 * reactive) < 1e-12
+    assert abs(out[R.LINK] - 0.3 * links / 6) < 1e-12
+
+
+def test_all_populations_variant_equals_node_reaction_with_neighbour_mean_rates():
+    # the variant is a node reaction whose per-node rate is the mean rate of
+    # the node's catalytic neighbours of each type (cascade, both types)
+    nx, ny = 48, 36
+    t = np.zeros((ny, nx), np.uint8)
+    own = rasterize(t, [(15, 18), (33, 17)], 4)
+    surf = classify_surface(t, own)
+    t[surf & (own == 0)] = CAT1
+    t[surf & (own == 1)] = CAT2
+    rng = np.random.default_rng(0)
+    k = np.where(surf, rng.uniform(0.05, 0.4, size=t.shape), 0.0)
+    k1 = np.zeros((ny, nx))
+    k2 = np.zeros((ny, nx))
+    for y in range(ny):
+        for x in range(nx):
+            if t[y, x] != 0:
+                continue
+            a = [k[(y + CY[i]) % ny, (x + CX[i]) % nx] for i in range(1, 5)
+                 if t[(y + CY[i]) % ny, (x + CX[i]) % nx] == CAT1]
+            b = [k[(y + CY[i]) % ny, (x + CX[i]) % nx] for i in range(1, 5)
+                 if t[(y + CY[i]) % ny, (x + CX[i]) % nx] == CAT2]
+            k1[y, x] = np.mean(a) if a else 0.0
+            k2[y, x] = np.mean(b) if b else 0.0
+    z = np.zeros((ny, nx))
+    bc = R.PERIODIC_X | R.PERIODIC_Y
+    ga = np.zeros((3, 5, ny, nx))
+    ga[0] = np.where(t == 0, _eq_state(np.ones((ny, nx)), 0, 0)[0], 0.0)
+    gb = ga.copy()
+    R.adr_run(t, k, z, z, ga, 0.8, 200, mode=R.NODE_AT_CATALYST, bc=bc)
+    R.adr_run(t, k1, z, z, gb, 0.8, 200, mode=R.NODE, bc=bc, k2=k2)
+    assert np.abs(ga - gb).max() < 1e-14
+    tot = R.adr_totals(t, ga)
+    assert abs(tot.sum() - (t == 0).sum()) < 1e-9   # closed box: A + B + C conserved
+    assert tot[2] > 0

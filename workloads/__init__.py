@@ -8,10 +8,10 @@ neither the GPU binding nor the oracle.
 from .geometry import (FLUID, SOLID, CAT1, CAT2, channel, disc_offsets, place_discs,
                        rasterize, classify_surface, surface_counts)
 from .configs import (U0, TAU_F, LatticeParams, lattice_params, Workload, make_workload,
-                      CONFIGS, batch_instances)
+                      CONFIGS, batch_instances, box_workload)
 
 __all__ = [
     "FLUID", "SOLID", "CAT1", "CAT2", "channel", "disc_offsets", "place_discs", "rasterize",
     "classify_surface", "surface_counts", "U0", "TAU_F", "LatticeParams", "lattice_params",
-    "Workload", "make_workload", "CONFIGS", "batch_instances",
+    "Workload", "make_workload", "CONFIGS", "batch_instances", "box_workload",
 ]

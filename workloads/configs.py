@@ -61,6 +61,7 @@ class Workload:
     adr_tol: float = 1e-8            # relative change of eps over check interval
     check_every: int = 1000
     centres: list = field(default_factory=list)
+    boundary: int = 0                # 0 channel with inlet/outlet, 1 periodic box (no flow)
 
     @property
     def nx(self) -> int:
@@ -160,6 +161,37 @@ def _two_discs(name, nx, ny, r, c1, c2, pe, da, real="f64"):
     surf = classify_surface(t, owner)
     t, k = _finish(t, owner, surf, lambda f, x, y: (CAT1, CAT2)[f], p.k)
     return Workload(name, t, k, 3, p, real=real, centres=[c1, c2])
+
+
+def box_workload(morphology: str = "pair", da: float = 150.0, d: float = 0.1, n: int = 300,
+                 xi: int = 100, real: str = "f64") -> Workload:
+    """Pure-diffusion cascade in an n x n box periodic in x and y (paper Sec.
+    "Pure diffusion case"): no flow, A fills the fluid homogeneously at t = 0,
+    and the totals of A, B, C are followed in time.
+
+    morphology "pair": two fibres R = 5 on the centre row, centres xi apart,
+    the left one carrying catalyst type 1 and the right one type 2 (the
+    "individual" arrangement).  "side": one fibre R = 10 at the centre, type 1
+    on its left half (x < cx) and type 2 on the right half (side-by-side).
+    D = (tau_g - 1/2)/3 is fixed by ``d``; k = Da D / R^2 with the fibre's R."""
+    t = np.zeros((n, n), dtype=np.uint8)
+    c = n // 2
+    if morphology == "pair":
+        r = 5
+        centres = [(c - xi // 2, c), (c + xi - xi // 2, c)]
+        kind = lambda f, x, y: (CAT1, CAT2)[f]
+    elif morphology == "side":
+        r = 10
+        centres = [(c, c)]
+        kind = lambda f, x, y: CAT1 if x < c else CAT2
+    else:
+        raise KeyError(morphology)
+    k = da * d / (r * r)
+    p = LatticeParams(0.0, da, r, d, 0.5 + 3.0 * d, k, 0.0)
+    owner = rasterize(t, centres, r)
+    surf = classify_surface(t, owner)
+    t, kmap = _finish(t, owner, surf, kind, k)
+    return Workload(f"box-{morphology}", t, kmap, 3, p, real=real, centres=centres, boundary=1)
 
 
 def make_workload(name: str, pe: float | None = None, da: float | None = None,
