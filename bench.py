@@ -188,7 +188,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--workload", default="C2")
     ap.add_argument("--pe", type=float, default=None)
-    ap.add_argument("--flow-max-steps", type=int, default=100000)
+    ap.add_argument("--flow-max-steps", type=int, default=400000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probe-copy-mib", type=int, default=1024)
     ap.add_argument("--no-adjoint", action="store_true")
@@ -220,7 +220,7 @@ def main():
     # ---- set-up: flow (a3), handoff + ADR initial state
     ctx.flow_init()
     t0 = time.perf_counter()
-    flow_steps, flow_res, flow_conv = ctx.flow_steady(args.flow_max_steps, 1000, w.flow_tol)
+    flow_steps, flow_res, flow_conv = ctx.flow_steady(args.flow_max_steps, 1000, w.flow_tolerance)
     flow_s = time.perf_counter() - t0
     flow_ms = ctx.time_flow_steps(1000)
     flow_mlups = w.nx * w.ny * 1000 / (flow_ms * 1e-3) / 1e6

@@ -57,7 +57,7 @@ class Workload:
     tau_f: float = TAU_F
     c_in: float = C_IN
     flow_steps: int | None = None    # fixed flow step count (None: run to tolerance)
-    flow_tol: float = 1e-6           # max|du| over check interval <= tol*u0
+    flow_tol: float | None = None    # max|du| over check interval <= tol*u0 (None: by precision)
     adr_tol: float = 1e-8            # relative change of eps over check interval
     check_every: int = 1000
     centres: list = field(default_factory=list)
@@ -70,6 +70,15 @@ class Workload:
     @property
     def ny(self) -> int:
         return self.node_type.shape[0]
+
+    @property
+    def flow_tolerance(self) -> float:
+        """Flow convergence tolerance: 1e-6 u0 in FP64; 1e-5 u0 with FP32
+        storage, whose rounding keeps max|du| over 1000 steps near 4e-6 u0 on
+        the C1/C2 lattices however long the flow runs."""
+        if self.flow_tol is not None:
+            return self.flow_tol
+        return 1e-5 if self.real == "f32" else 1e-6
 
     @property
     def tau_g(self) -> float:
