@@ -27,33 +27,35 @@ __device__ __forceinline__ Real inlet_u(int y, int ny, double u0)
 }
 
 // Collide the shifted populations h in place; returns (u, v) and writes them.
-// f_eq - w = w (drho + rho (3 cu + 4.5 cu^2 - 1.5 u.u)): opposite directions
-// share the even part (drho + rho (4.5 cu^2 - 1.5 u.u)) and differ in the sign
-// of the odd part 3 rho cu, so each pair costs one evaluation.
+// f_eq - w = w (drho + rho X) with X = 3 cu + 4.5 cu^2 - 1.5 u.u.  Opposite
+// directions share the even part of X and differ in the sign of 3 cu, so each
+// pair costs one evaluation.  Every product with rho = 1 + drho is formed as
+// X + drho X, and 1/rho as 1 + d with d = -drho/(1 + drho): in FP32 the
+// rounding of 1 + drho itself is then never used.  (drho changes by less
+// than an ulp of 1 between neighbouring nodes, so that rounding error is
+// smooth in space and would bias the steady state.)
 template <typename Real>
 __device__ __forceinline__ void collide(Real (&h)[9], Real omega, Real &u, Real &v)
 {
     const Real drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
     const Real jx = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
     const Real jy = (h[2] - h[4]) + (h[5] - h[8]) + (h[6] - h[7]);
-    const Real rho = Real(1) + drho;
-    const Real inv = Real(1) / rho;
-    u = jx * inv;
-    v = jy * inv;
+    const Real d = -drho / (Real(1) + drho);
+    u = jx + jx * d;
+    v = jy + jy * d;
     const Real uu = Real(1.5) * (u * u + v * v);
-    const Real r3 = Real(3) * rho;
-    const Real r45 = Real(4.5) * rho;
-    const Real base = drho - rho * uu;
     Real eq[9];
-    eq[0] = wgt<Real>(0) * base;
+    eq[0] = wgt<Real>(0) * (drho - (uu + drho * uu));
     // cu per pair (direction, opposite): (E, W) u; (N, S) v; (NE, SW) u + v; (NW, SE) v - u
     const Real cu[4] = {u, v, u + v, v - u};
     const int dir[4] = {1, 2, 5, 6}, opp[4] = {3, 4, 7, 8};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const Real w = wgt<Real>(dir[q]);
-        const Real even = base + r45 * cu[q] * cu[q];
-        const Real odd = r3 * cu[q];
+        const Real xe = Real(4.5) * cu[q] * cu[q] - uu;
+        const Real xo = Real(3) * cu[q];
+        const Real even = drho + (xe + drho * xe);
+        const Real odd = xo + drho * xo;
         eq[dir[q]] = w * (even + odd);
         eq[opp[q]] = w * (even - odd);
     }
@@ -84,11 +86,15 @@ __device__ __forceinline__ void node_update(const FlowArgs<Real> &a, int x, int 
     if (x == 0) {
         // Zou-He velocity inlet, u = (u_in(y), 0): unknown E, NE, SE.
         // In shifted form the known sum f0+fN+fS+2(fW+fNW+fSW) is 1 + sum h.
+        // rho - 1 = (S + ux)/(1 - ux) with S the known shifted sum, so that
+        // rho ux = ux + (rho - 1) ux never rounds 1 + (rho - 1) on its own.
         const Acc ux = inlet_u<Acc>(y, a.ny, a.u0);
-        const Acc rho = (Acc(1) + h[0] + h[2] + h[4] + Acc(2) * (h[3] + h[6] + h[7])) / (Acc(1) - ux);
-        h[1] = h[3] + Acc(2) / Acc(3) * rho * ux;
-        h[5] = h[7] - Acc(0.5) * (h[2] - h[4]) + rho * ux / Acc(6);
-        h[8] = h[6] + Acc(0.5) * (h[2] - h[4]) + rho * ux / Acc(6);
+        const Acc S = h[0] + h[2] + h[4] + Acc(2) * (h[3] + h[6] + h[7]);
+        const Acc drho = (S + ux) / (Acc(1) - ux);
+        const Acc rux = ux + drho * ux;
+        h[1] = h[3] + Acc(2) / Acc(3) * rux;
+        h[5] = h[7] - Acc(0.5) * (h[2] - h[4]) + rux / Acc(6);
+        h[8] = h[6] + Acc(0.5) * (h[2] - h[4]) + rux / Acc(6);
     } else if (x == a.nx - 1) {
         // Zou-He pressure outlet, rho = 1, u_y = 0: unknown W, NW, SW
         const Acc ux = h[0] + h[2] + h[4] + Acc(2) * (h[1] + h[5] + h[8]);
