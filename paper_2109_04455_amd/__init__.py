@@ -14,7 +14,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import LbfParams
+from ._lib import Lbf3Params, LbfParams
 
 __all__ = ["LbfError", "LbfNotConverged", "Context", "Batch", "params", "lib", "probe_copy",
            "workspace_tensor"]
@@ -262,6 +262,142 @@ class Context:
     def time_flow_steps(self, nsteps):
         ms = ctypes.c_double()
         self._call("lbf_time_flow_steps", int(nsteps), ctypes.byref(ms))
+        return ms.value
+
+
+def params3d(nx, ny, nz, *, real="f32", nspecies=3, tau_f=0.8, force_x=1e-6, tau_g=0.8,
+             c_in=1.0, vel_scale=1.0, flux_col=-1, flags=0) -> Lbf3Params:
+    p = Lbf3Params()
+    _check(lib().lbf3_params_default(ctypes.byref(p), nx, ny, nz))
+    p.real_bytes = {"f32": 4, "f64": 8}[real]
+    p.nspecies = nspecies
+    p.tau_f, p.force_x, p.tau_g, p.c_in, p.vel_scale = tau_f, force_x, tau_g, c_in, vel_scale
+    p.flux_col, p.flags = flux_col, flags
+    return p
+
+
+class Context3D:
+    """One 3D lattice (fields ``[nz, ny, nx]``): forced periodic D3Q19 flow,
+    D3Q7 ADR with inlet/outlet in x, observables."""
+
+    def __init__(self, p: Lbf3Params, device="cuda", stream=None):
+        self.p = p
+        self.device = torch.device(device)
+        self.real = {4: torch.float32, 8: torch.float64}[p.real_bytes]
+        self.shape = (p.nz, p.ny, p.nx)
+        self.ns = p.nspecies
+        h = ctypes.c_void_p()
+        st = lib().lbf3_create(ctypes.byref(p), ctypes.byref(h))
+        self._h = h
+        if st != _lib.OK:
+            msg = lib().lbf3_last_error(h).decode()
+            lib().lbf3_destroy(h)
+            self._h = None
+            raise LbfError(st, f"lbf3_create: {lib().lbf_status_str(st).decode()}: {msg}")
+        nbytes = ctypes.c_size_t()
+        self._call("lbf3_workspace_bytes", ctypes.byref(nbytes))
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._ws, ptr = workspace_tensor(nbytes.value, self.device)
+        self._call("lbf3_bind", ctypes.c_void_p(ptr), nbytes.value, _stream_handle(self.stream))
+        self._keep = []
+
+    def _call(self, name, *args):
+        st = getattr(lib(), name)(self._h, *args)
+        if st != _lib.OK:
+            detail = lib().lbf3_last_error(self._h).decode()
+            cls = LbfNotConverged if st == _lib.ENOTCONV else LbfError
+            raise cls(st, f"{name}: {lib().lbf_status_str(st).decode()}: {detail}")
+
+    def _dev(self, a, dtype):
+        return torch.as_tensor(a).to(device=self.device, dtype=dtype).contiguous()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            torch.cuda.synchronize(self.device)
+            lib().lbf3_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_geometry(self, node_type):
+        t = self._dev(node_type, torch.uint8)
+        assert tuple(t.shape) == self.shape
+        with torch.cuda.stream(self.stream):
+            self._call("lbf3_set_geometry", ctypes.c_void_p(t.data_ptr()))
+
+    def set_rates(self, k):
+        t = self._dev(k, torch.float64)
+        assert tuple(t.shape) == self.shape
+        with torch.cuda.stream(self.stream):
+            self._call("lbf3_set_rates", ctypes.c_void_p(t.data_ptr()))
+
+    def flow_init(self):
+        self._call("lbf3_flow_init")
+
+    def flow_run(self, nsteps):
+        self._call("lbf3_flow_run", int(nsteps))
+
+    def flow_steady(self, max_steps, check_every=1000, tol=1e-5):
+        """Returns (steps, residual, converged)."""
+        steps, res = ctypes.c_long(), ctypes.c_double()
+        st = lib().lbf3_flow_steady(self._h, int(max_steps), int(check_every), float(tol),
+                                    ctypes.byref(steps), ctypes.byref(res))
+        if st not in (_lib.OK, _lib.ENOTCONV):
+            raise LbfError(st, lib().lbf3_last_error(self._h).decode())
+        return steps.value, res.value, st == _lib.OK
+
+    def get_velocity(self):
+        u = [torch.empty(self.shape, dtype=self.real, device=self.device) for _ in range(3)]
+        self._call("lbf3_get_velocity", *[ctypes.c_void_p(t.data_ptr()) for t in u])
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return torch.stack(u)
+
+    def set_velocity(self, u):
+        ts = [self._dev(u[c], self.real) for c in range(3)]
+        with torch.cuda.stream(self.stream):
+            self._call("lbf3_set_velocity", *[ctypes.c_void_p(t.data_ptr()) for t in ts])
+        self._keep = ts
+
+    def adr_init(self):
+        self._call("lbf3_adr_init")
+
+    def adr_run(self, max_steps, check_every=1000, tol=0.0):
+        steps = ctypes.c_long()
+        st = lib().lbf3_adr_run(self._h, int(max_steps), int(check_every), float(tol),
+                                ctypes.byref(steps))
+        if st not in (_lib.OK, _lib.ENOTCONV):
+            raise LbfError(st, lib().lbf3_last_error(self._h).decode())
+        return steps.value, st == _lib.OK
+
+    def efficiency(self):
+        eps, inflow = ctypes.c_double(), ctypes.c_double()
+        n = (ctypes.c_double * 3)()
+        self._call("lbf3_efficiency", ctypes.byref(eps), n, ctypes.byref(inflow))
+        return eps.value, np.array(n[: self.ns]), inflow.value
+
+    def concentration(self, species):
+        out = torch.empty(self.shape, dtype=self.real, device=self.device)
+        self._call("lbf3_get_concentration", int(species), ctypes.c_void_p(out.data_ptr()))
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return out
+
+    def totals(self):
+        t = (ctypes.c_double * 3)()
+        self._call("lbf3_adr_totals", t)
+        return np.array(t[: self.ns])
+
+    def time_adr_steps(self, nsteps):
+        ms = ctypes.c_double()
+        self._call("lbf3_time_adr_steps", int(nsteps), ctypes.byref(ms))
+        return ms.value
+
+    def time_flow_steps(self, nsteps):
+        ms = ctypes.c_double()
+        self._call("lbf3_time_flow_steps", int(nsteps), ctypes.byref(ms))
         return ms.value
 
 

@@ -27,6 +27,17 @@ class LbfParams(ctypes.Structure):
     ]
 
 
+class Lbf3Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("real_bytes", ctypes.c_int), ("nspecies", ctypes.c_int),
+        ("tau_f", ctypes.c_double), ("force_x", ctypes.c_double),
+        ("tau_g", ctypes.c_double), ("c_in", ctypes.c_double),
+        ("vel_scale", ctypes.c_double),
+        ("flux_col", ctypes.c_int), ("flags", ctypes.c_int),
+    ]
+
+
 # name -> (restype, argtypes)
 _P, _I, _L, _D, _S = ctypes.c_void_p, ctypes.c_int, ctypes.c_long, ctypes.c_double, ctypes.c_size_t
 _PP = ctypes.POINTER(LbfParams)
@@ -74,6 +85,27 @@ SIGNATURES = {
     "lbf_batch_time_steps": (_I, [_P, _L, _PD]),
     "lbf_batch_last_error": (ctypes.c_char_p, [_P]),
     "lbf_batch_destroy": (None, [_P]),
+    # 3D path (include/lbf3d.h)
+    "lbf3_params_default": (_I, [ctypes.POINTER(Lbf3Params), _I, _I, _I]),
+    "lbf3_create": (_I, [ctypes.POINTER(Lbf3Params), ctypes.POINTER(_P)]),
+    "lbf3_workspace_bytes": (_I, [_P, _PS]),
+    "lbf3_bind": (_I, [_P, _P, _S, _P]),
+    "lbf3_set_geometry": (_I, [_P, _P]),
+    "lbf3_set_rates": (_I, [_P, _P]),
+    "lbf3_flow_init": (_I, [_P]),
+    "lbf3_flow_run": (_I, [_P, _L]),
+    "lbf3_flow_steady": (_I, [_P, _L, _I, _D, _PL, _PD]),
+    "lbf3_get_velocity": (_I, [_P, _P, _P, _P]),
+    "lbf3_set_velocity": (_I, [_P, _P, _P, _P]),
+    "lbf3_adr_init": (_I, [_P]),
+    "lbf3_adr_run": (_I, [_P, _L, _I, _D, _PL]),
+    "lbf3_efficiency": (_I, [_P, _PD, _PD, _PD]),
+    "lbf3_get_concentration": (_I, [_P, _I, _P]),
+    "lbf3_adr_totals": (_I, [_P, _PD]),
+    "lbf3_time_adr_steps": (_I, [_P, _L, _PD]),
+    "lbf3_time_flow_steps": (_I, [_P, _L, _PD]),
+    "lbf3_last_error": (ctypes.c_char_p, [_P]),
+    "lbf3_destroy": (None, [_P]),
 }
 
 _lib = None

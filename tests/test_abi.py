@@ -1,20 +1,27 @@
 """The C-ABI library without a GPU: it loads, exports every entry point that
-include/lbf.h declares, and its host-side validation rejects bad arguments
+include/*.h declare, and its host-side validation rejects bad arguments
 before any HIP call."""
 import ctypes
+import glob
 import os
 import re
 
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "lbf.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("lbf.h", "lbf3d.h")]
 
 
 def _declared():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbf_[a-z_0-9]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(lbf3?_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_every_header_is_scanned():
+    assert sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))) == sorted(HEADERS)
 
 
 @pytest.fixture(scope="module")
@@ -99,6 +106,42 @@ def test_reaction_variant_and_periodic_box_accepted(L):
     for kw in (dict(reaction_mode=1), dict(boundary=1), dict(reaction_mode=1, boundary=1, real_bytes=8)):
         st, msg = _create(L, _params(L, **kw))
         assert st == 0, msg
+
+
+def _params3(L, **kw):
+    from paper_2109_04455_amd._lib import Lbf3Params
+    p = Lbf3Params()
+    assert L.lbf3_params_default(ctypes.byref(p), 40, 24, 20) == 0
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("field,value,needle", [
+    ("nx", 4, "nx >= 8"), ("nz", 1, "nz >= 2"), ("real_bytes", 2, "real_bytes"),
+    ("nspecies", 1, "nspecies"), ("tau_f", 0.5, "tau_f"), ("tau_g", 0.2, "tau_g"),
+    ("force_x", 0.1, "force_x"), ("vel_scale", -1.0, "vel_scale"), ("flux_col", 39, "flux_col"),
+])
+def test_3d_invalid_parameters_rejected(L, field, value, needle):
+    h = ctypes.c_void_p()
+    st = L.lbf3_create(ctypes.byref(_params3(L, **{field: value})), ctypes.byref(h))
+    msg = L.lbf3_last_error(h).decode()
+    L.lbf3_destroy(h)
+    assert st == -1 and needle in msg
+
+
+def test_3d_workspace_arithmetic(L):
+    h = ctypes.c_void_p()
+    assert L.lbf3_create(ctypes.byref(_params3(L)), ctypes.byref(h)) == 0
+    n = ctypes.c_size_t()
+    assert L.lbf3_workspace_bytes(h, ctypes.byref(n)) == 0
+    plane = 64 * 24 * 20
+    # type, D3Q7 and D3Q19 masks, rates, two D3Q19 and two 3-species D3Q7
+    # lattices, three velocity blocks
+    expect = plane * (1 + 2 + 4 + 4 + 2 * 19 * 4 + 2 * 21 * 4 + 3 * 3 * 4)
+    assert expect <= n.value <= expect + 64 * 1024
+    assert L.lbf3_flow_init(h) == -6          # no workspace bound yet
+    L.lbf3_destroy(h)
 
 
 def test_status_strings(L):
