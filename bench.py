@@ -181,6 +181,104 @@ def batch_leg(steps=2000, flow_steps=2000):
             "batched_total_s": round(b["seconds"], 3), "serial_total_s": round(s["seconds"], 3),
             "identical_results": same}
 
+def membrane3d_leg(steps=2000):
+    """3D randomly oriented fibre membranes (D3Q19 forced flow, D3Q7 ADR, FP32
+    storage).  Throughput and HBM roofline of both step kernels on the paper's
+    cascade membrane doubled in every direction (400x120x120, 1.05 GB of ADR
+    lattices); time to the steady efficiency on the paper's own 200x60x60 box."""
+    import torch
+    import paper_2109_04455_amd as L
+    from workloads.configs3d import make_workload3d
+    out = {}
+    w = make_workload3d("M3c2")
+    n = w.nx * w.ny * w.nz
+    fluid = int((w.node_type == 0).sum())
+    p = L.params3d(w.nx, w.ny, w.nz, real="f32", nspecies=3, tau_f=w.tau_f, force_x=w.force,
+                   tau_g=w.tau_g)
+    c = L.Context3D(p)
+    c.set_geometry(w.node_type)
+    c.set_rates(w.k)
+    c.flow_init()
+    c.flow_run(200)
+    flow_ms = c.time_flow_steps(steps) / steps
+    c.adr_init()
+    c.adr_run(200, check_every=200, tol=0)
+    adr_ms = c.time_adr_steps(steps) / steps
+    adr_b = fluid * (2 * 21 * 4 + 3 * 4 + 2) + (n - fluid) * 2
+    flow_b = fluid * (2 * 19 * 4 + 4) + (n - fluid) * 4
+    out["M3c2"] = {
+        "lattice": [w.nx, w.ny, w.nz], "fibres": 96, "steps": steps,
+        "adr_us": round(adr_ms * 1e3, 2), "adr_mlups": round(n / adr_ms / 1e3, 1),
+        "adr_gbs": round(adr_b / adr_ms / 1e6, 1), "adr_frac": round(adr_b / adr_ms / 1e6 / PEAK_HBM_GBS, 4),
+        "adr_bytes_per_fluid_node": 182,
+        "flow_us": round(flow_ms * 1e3, 2), "flow_mlups": round(n / flow_ms / 1e3, 1),
+        "flow_gbs": round(flow_b / flow_ms / 1e6, 1),
+        "flow_frac": round(flow_b / flow_ms / 1e6 / PEAK_HBM_GBS, 4), "flow_bytes_per_fluid_node": 156}
+    c.close()
+    w = make_workload3d("M3c")
+    p = L.params3d(w.nx, w.ny, w.nz, real="f32", nspecies=3, tau_f=w.tau_f, force_x=w.force,
+                   tau_g=w.tau_g)
+    c = L.Context3D(p)
+    c.set_geometry(w.node_type)
+    c.set_rates(w.k)
+    c.flow_init()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fsteps, fres, fconv = c.flow_steady(200000, 1000, 1e-5)
+    u = c.get_velocity()
+    vs = w.vel_scale(u[0].double().cpu().numpy())
+    c.close()
+    # the ADR runs on the same flow, scaled to the entrance velocity of Pe
+    p.vel_scale = vs
+    c = L.Context3D(p)
+    c.set_geometry(w.node_type)
+    c.set_rates(w.k)
+    c.set_velocity(u)
+    c.adr_init()
+    asteps, aconv = c.adr_run(400000, check_every=1000, tol=1e-6)
+    eps, N, inflow = c.efficiency()
+    torch.cuda.synchronize()
+    out["M3c"] = {"lattice": [w.nx, w.ny, w.nz], "pe": w.params.pe, "da": w.params.da,
+                  "flow_steps": fsteps, "flow_converged": fconv, "vel_scale": round(vs, 3),
+                  "adr_steps": asteps, "adr_converged": aconv, "eps": eps,
+                  "mass_balance": float(abs(N.sum() - inflow) / inflow),
+                  "seconds_to_solution": round(time.perf_counter() - t0, 2)}
+    c.close()
+    return out
+
+
+def no_flow_leg(steps=(10000, 50000, 100000)):
+    """The paper's pure-diffusion cascade (300x300 periodic box, Da 150, no
+    flow): total C over time for two fibres 100 apart vs one side-by-side
+    fibre of the same catalytic surface."""
+    import torch
+    import paper_2109_04455_amd as L
+    from workloads import box_workload
+    res = {}
+    for morph in ("pair", "side"):
+        w = box_workload(morph, real="f32")
+        p = L.params(w.nx, w.ny, real="f32", nspecies=3, tau_g=w.tau_g, c_in=w.c_in,
+                     vel_scale=0.0, boundary=L.PERIODIC)
+        c = L.Context(p)
+        c.set_geometry(w.node_type)
+        c.set_rates(w.k)
+        z = torch.zeros((w.ny, w.nx), dtype=torch.float32)
+        c.set_velocity(z, z)
+        c.adr_init()
+        done, series = 0, []
+        t0 = time.perf_counter()
+        for s in steps:
+            c.adr_run(s - done, check_every=s - done, tol=0)
+            done = s
+            tot = c.totals()
+            series.append([s, float(tot[2] / tot.sum())])
+        res[morph] = {"C_fraction": series, "seconds": round(time.perf_counter() - t0, 3)}
+        c.close()
+    res["side_by_side_faster"] = all(b[1] > a[1] for a, b in zip(res["pair"]["C_fraction"],
+                                                                  res["side"]["C_fraction"]))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +294,8 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=20000)
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--no-noflow", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -287,6 +387,10 @@ def main():
         out["batched_sweep"] = batch_leg(args.batch_steps)
     if not args.no_precision:
         out["fp32_vs_fp64"] = precision_leg()
+    if not args.no_3d:
+        out["membrane_3d"] = membrane3d_leg()
+    if not args.no_noflow:
+        out["no_flow_box"] = no_flow_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

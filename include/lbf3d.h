@@ -47,6 +47,9 @@ typedef struct {
     double c_in;         /* inlet concentration of A                            */
     double vel_scale;    /* ADR velocity = vel_scale * flow velocity, >= 0      */
     int flux_col;        /* flux face between flux_col and flux_col+1; -1: nx-3 */
+    int tile_x, tile_y;  /* thread block: tile_x nodes along x times tile_y rows
+                            (y, z lines); 0: 64 x 4.  tile_x * tile_y must be a
+                            multiple of 64 and <= 1024                          */
     int flags;           /* bit 0: no XCD-aware block order; bit 1: cached
                             population accesses; bit 4: FP32 arithmetic;
                             bit 6: streaming accesses even when the lattices
@@ -54,7 +57,8 @@ typedef struct {
 } lbf3_params;
 
 /* Defaults for an nx x ny x nz lattice: FP32, 3 species, tau_f 0.8,
- * force 1e-6, tau_g 0.8, c_in 1, vel_scale 1, flux_col -1, flags 0. */
+ * force 1e-6, tau_g 0.8, c_in 1, vel_scale 1, flux_col -1, tiles 64 x 4,
+ * flags 0. */
 lbf_status lbf3_params_default(lbf3_params *p, int nx, int ny, int nz);
 /* Validate (host only) and create; a context is returned even on
  * LBF_EINVAL so that lbf3_last_error can explain. */

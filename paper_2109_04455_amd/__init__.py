@@ -266,13 +266,13 @@ class Context:
 
 
 def params3d(nx, ny, nz, *, real="f32", nspecies=3, tau_f=0.8, force_x=1e-6, tau_g=0.8,
-             c_in=1.0, vel_scale=1.0, flux_col=-1, flags=0) -> Lbf3Params:
+             c_in=1.0, vel_scale=1.0, flux_col=-1, tile_x=0, tile_y=0, flags=0) -> Lbf3Params:
     p = Lbf3Params()
     _check(lib().lbf3_params_default(ctypes.byref(p), nx, ny, nz))
     p.real_bytes = {"f32": 4, "f64": 8}[real]
     p.nspecies = nspecies
     p.tau_f, p.force_x, p.tau_g, p.c_in, p.vel_scale = tau_f, force_x, tau_g, c_in, vel_scale
-    p.flux_col, p.flags = flux_col, flags
+    p.flux_col, p.tile_x, p.tile_y, p.flags = flux_col, tile_x, tile_y, flags
     return p
 
 

@@ -34,7 +34,8 @@ class Lbf3Params(ctypes.Structure):
         ("tau_f", ctypes.c_double), ("force_x", ctypes.c_double),
         ("tau_g", ctypes.c_double), ("c_in", ctypes.c_double),
         ("vel_scale", ctypes.c_double),
-        ("flux_col", ctypes.c_int), ("flags", ctypes.c_int),
+        ("flux_col", ctypes.c_int), ("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int),
+        ("flags", ctypes.c_int),
     ]
 
 

@@ -121,6 +121,7 @@ def _params3(L, **kw):
     ("nx", 4, "nx >= 8"), ("nz", 1, "nz >= 2"), ("real_bytes", 2, "real_bytes"),
     ("nspecies", 1, "nspecies"), ("tau_f", 0.5, "tau_f"), ("tau_g", 0.2, "tau_g"),
     ("force_x", 0.1, "force_x"), ("vel_scale", -1.0, "vel_scale"), ("flux_col", 39, "flux_col"),
+    ("tile_x", 100, "tile_x"), ("tile_y", 5, "tile_x"),
 ])
 def test_3d_invalid_parameters_rejected(L, field, value, needle):
     h = ctypes.c_void_p()
