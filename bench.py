@@ -247,6 +247,31 @@ def membrane3d_leg(steps=2000):
     return out
 
 
+def rwpt_leg(w, ux, uy, steps=200, density=10.0):
+    """The GPU random-walk tracker on the same geometry and flow as the
+    headline ADR run: particle-steps per second and the bytes a step moves
+    per particle (compaction: 8 B read to count, 25 B read + 25 B written to
+    scatter; move: 25 B read + 17 B written)."""
+    import torch
+    import paper_2109_04455_amd as L
+    p = L.rw_params(w.nx, w.ny, nspecies=w.nspecies, D=w.params.d, vel_scale=w.vel_scale,
+                    density=density, seed=5)
+    r = L.RandomWalk(p)
+    r.set_fields(w.node_type, ux.double(), uy.double(), w.k)
+    r.fill()
+    r.run(50)
+    ms = r.time_steps(steps, measure=True)
+    n, held, _ = r.counts()
+    r.close()
+    per_step = ms * 1e-3 / steps
+    bytes_pp = 8 + 50 + 42
+    return {"workload": f"{w.name} geometry and flow, density {density} per unit area",
+            "particles": held, "steps": steps, "us_per_step": round(per_step * 1e6, 1),
+            "particle_steps_per_s": round(held / per_step, 1),
+            "gbs": round(held * bytes_pp / per_step / 1e9, 1), "bytes_per_particle_step": bytes_pp,
+            "N": [float(v) for v in n]}
+
+
 def no_flow_leg(steps=(10000, 50000, 100000)):
     """The paper's pure-diffusion cascade (300x300 periodic box, Da 150, no
     flow): total C over time for two fibres 100 apart vs one side-by-side
@@ -296,6 +321,7 @@ def main():
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--no-noflow", action="store_true")
+    ap.add_argument("--no-rwpt", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -380,6 +406,9 @@ def main():
                  "gbs": round(flow_bytes_per_step(w.node_type, real_bytes) / (flow_ms * 1e-3 / 1000) / 1e9, 1)},
         "copy_probe_gbs": round(copy_gbs, 1),
     }
+    if not args.no_rwpt:
+        ux, uy = ctx.get_velocity()
+        out["rwpt"] = rwpt_leg(w, ux, uy)
     ctx.close()
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(args.adjoint_steps)

@@ -21,25 +21,36 @@
  *     of species A every step (Dirichlet inlet); B and C are reflected at the
  *     inlet plane; particles leave through the outlet plane;
  *   - N_s = net number of crossings of the plane xf + 1/2 per unit time.
- * Random numbers: splitmix64 (Steele, Lea & Flood, 2014).
+ * Random numbers: splitmix64 (Steele, Lea & Flood, 2014) used as a
+ * counter-based generator: every particle has a 64-bit id, and draw d of step
+ * t is output n = 8 t + d + 1 of splitmix64 started from the state
+ * seed ^ mix(id).  A particle's path therefore depends only on its id, its
+ * state and the step, not on the order in which particles are processed.
+ * Ids: the j-th particle of the initial fill of fluid cell c is c * 256 + j
+ * (the count of cell c is drawn from id 2^63 + c); the j-th reservoir particle
+ * inserted at step t is 2^62 + t * 2^24 + j.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 
-typedef struct {
-    uint64_t s;
-} rng_t;
-
-static uint64_t rng_next(rng_t *r)
+static uint64_t mix(uint64_t z)
 {
-    uint64_t z = (r->s += 0x9e3779b97f4a7c15ULL);
     z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
     z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
     return z ^ (z >> 31);
 }
 
-static double unif(rng_t *r) { return (double)(rng_next(r) >> 11) * (1.0 / 9007199254740992.0); }
+/* draw d of step t of particle id, uniform in [0, 1) */
+static double draw(uint64_t seed, uint64_t id, uint64_t t, unsigned d)
+{
+    uint64_t state = seed ^ mix(id);
+    uint64_t n = 8 * t + d + 1;
+    return (double)(mix(state + n * 0x9e3779b97f4a7c15ULL) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+#define ID_INSERT (1ULL << 62)
+#define ID_COUNT (1ULL << 63)
 
 typedef struct {
     int nx, ny;
@@ -141,6 +152,60 @@ static void reflect(const geom_t *g, double px, double py, double *qx, double *q
  *   out[ns]     number of particles in the domain at the end
  *   wall_mode   velocity interpolation next to solids (see interp)
  */
+/* One step of one particle (advect, diffuse, reflect, inlet rule, crossing
+ * count, reaction).  Returns 1 if it left through the outlet.  *cross_ds
+ * receives the signed crossing of the measuring plane (+1, -1 or 0). */
+static int move_particle(const geom_t *g, int ns, uint64_t seed, uint64_t id, uint64_t t,
+                         double dt, double step_len, double zone, double rate_w, double buf_hi,
+                         double plane, int wall_mode, double *px, double *py, uint8_t *sp,
+                         int *cross_ds)
+{
+    static const int DX[4] = {1, 0, -1, 0}, DY[4] = {0, 1, 0, -1};
+    const int nx = g->nx, ny = g->ny;
+    double x0 = *px, y0 = *py;
+    double u = g->vel_scale * interp(g, g->ux, x0, y0, wall_mode);
+    double v = g->vel_scale * interp(g, g->uy, x0, y0, wall_mode);
+    double th = 2.0 * M_PI * draw(seed, id, t, 0);
+    double x1 = x0 + u * dt + step_len * cos(th);
+    double y1 = y0 + v * dt + step_len * sin(th);
+    reflect(g, x0, y0, &x1, &y1);
+    int s = *sp;
+    if (x1 < buf_hi && x0 >= buf_hi && s != 0) /* B, C: reflect at the inlet */
+        x1 = 2.0 * buf_hi - x1;
+    *cross_ds = (x0 < plane && x1 >= plane) ? 1 : ((x0 >= plane && x1 < plane) ? -1 : 0);
+    /* reaction next to catalytic faces of the current cell */
+    int cx = cell(x1), cy = cell(y1);
+    if (cx >= 0 && cx < nx && cy >= 0 && cy < ny && g->type[(size_t)cy * nx + cx] == 0) {
+        for (int d = 0; d < 4; ++d) {
+            int sx = cx + DX[d], sy = cy + DY[d];
+            if (sx < 0 || sx >= nx || sy < 0 || sy >= ny) continue;
+            int ty = g->type[(size_t)sy * nx + sx];
+            int src = ty == 2 ? 0 : (ty == 3 && ns == 3 ? 1 : -1);
+            if (src != s) continue;
+            double dist = d == 0 ? cx + 0.5 - x1 : d == 1 ? cy + 0.5 - y1
+                        : d == 2 ? x1 - (cx - 0.5) : y1 - (cy - 0.5);
+            if (dist >= zone) continue;
+            double p = g->k[(size_t)sy * nx + sx] * rate_w * dt / zone;
+            if (draw(seed, id, t, 1 + d) < p) {
+                *sp = (uint8_t)(src + 1);
+                break;
+            }
+        }
+    }
+    *px = x1;
+    *py = y1;
+    return x1 >= nx - 0.5;
+}
+
+/*
+ * Run the tracker.  Returns 0, or -1 on bad arguments / particle overflow.
+ *   c_density   reservoir particles per unit area of species A (<= 200)
+ *   zone        reactive zone width next to a catalytic face (<= 1)
+ *   rate_w      surface rate per unit length = k(sigma) * rate_w
+ *   out[0..ns)  net crossings of xf + 1/2 per unit time over the measurement
+ *   out[ns]     number of particles in the domain at the end
+ *   wall_mode   velocity interpolation next to solids (see interp)
+ */
 int rwpt_run(int nx, int ny, int ns, const uint8_t *type, const double *ux, const double *uy,
              double vel_scale, double D, const double *k, double rate_w, double c_density,
              double dt, double zone, int xf, long burn_steps, long meas_steps, uint64_t seed,
@@ -148,12 +213,13 @@ int rwpt_run(int nx, int ny, int ns, const uint8_t *type, const double *ux, cons
 {
     geom_t g = {nx, ny, type, ux, uy, k, vel_scale, 0.0};
     double step_len = sqrt(4.0 * D * dt);
-    if (ns < 2 || ns > 3 || zone <= 0 || zone > 1 || step_len >= 0.9) return -1;
+    if (ns < 2 || ns > 3 || zone <= 0 || zone > 1 || step_len >= 0.9 || c_density > 200)
+        return -1;
     double *px = malloc(sizeof(double) * max_particles);
     double *py = malloc(sizeof(double) * max_particles);
     uint8_t *sp = malloc(max_particles);
+    uint64_t *pid = malloc(sizeof(uint64_t) * max_particles);
     long np = 0;
-    rng_t r = {seed};
     const double buf_lo = -1.5, buf_hi = -0.5; /* reservoir strip */
     const double ylo = 0.5, yhi = ny - 1.5;    /* fluid band between wall rows */
     long buf_count = lround(c_density * (buf_hi - buf_lo) * (yhi - ylo));
@@ -164,76 +230,49 @@ int rwpt_run(int nx, int ny, int ns, const uint8_t *type, const double *ux, cons
     /* start from a uniform field of A in every fluid cell */
     for (int y = 0; y < ny && status == 0; ++y)
         for (int x = 0; x < nx; ++x) {
-            if (type[(size_t)y * nx + x] != 0) continue;
-            double area = 1.0;
-            long n = (long)floor(c_density * area + unif(&r));
+            uint64_t c = (uint64_t)y * nx + x;
+            if (type[c] != 0) continue;
+            long n = (long)floor(c_density + draw(seed, ID_COUNT + c, 0, 0));
             for (long j = 0; j < n; ++j) {
                 if (np >= max_particles) { status = -1; break; }
-                px[np] = x - 0.5 + unif(&r);
-                py[np] = y - 0.5 + unif(&r);
+                uint64_t id = c * 256 + (uint64_t)j;
+                px[np] = x - 0.5 + draw(seed, id, 0, 6);
+                py[np] = y - 0.5 + draw(seed, id, 0, 7);
                 sp[np] = 0;
+                pid[np] = id;
                 ++np;
             }
         }
-    static const int DX[4] = {1, 0, -1, 0}, DY[4] = {0, 1, 0, -1};
     for (long t = 0; t < burn_steps + meas_steps && status == 0; ++t) {
         int measuring = t >= burn_steps;
         /* refill the reservoir: drop its particles, place a fresh uniform set */
         for (long j = 0; j < np;) {
             if (px[j] < buf_hi) {
                 --np;
-                px[j] = px[np]; py[j] = py[np]; sp[j] = sp[np];
+                px[j] = px[np]; py[j] = py[np]; sp[j] = sp[np]; pid[j] = pid[np];
             } else {
                 ++j;
             }
         }
         for (long j = 0; j < buf_count; ++j) {
             if (np >= max_particles) { status = -1; break; }
-            px[np] = buf_lo + (buf_hi - buf_lo) * unif(&r);
-            py[np] = ylo + (yhi - ylo) * unif(&r);
+            uint64_t id = ID_INSERT + ((uint64_t)t << 24) + (uint64_t)j;
+            px[np] = buf_lo + (buf_hi - buf_lo) * draw(seed, id, 0, 6);
+            py[np] = ylo + (yhi - ylo) * draw(seed, id, 0, 7);
             sp[np] = 0;
+            pid[np] = id;
             ++np;
         }
         for (long j = 0; j < np;) {
-            double x0 = px[j], y0 = py[j];
-            double u = vel_scale * interp(&g, ux, x0, y0, wall_mode), v = vel_scale * interp(&g, uy, x0, y0, wall_mode);
-            double th = 2.0 * M_PI * unif(&r);
-            double x1 = x0 + u * dt + step_len * cos(th);
-            double y1 = y0 + v * dt + step_len * sin(th);
-            reflect(&g, x0, y0, &x1, &y1);
-            int s = sp[j];
-            if (x1 < buf_hi && x0 >= buf_hi && s != 0) /* B, C: reflect at the inlet */
-                x1 = 2.0 * buf_hi - x1;
-            if (measuring) {
-                if (x0 < plane && x1 >= plane) cross[s] += 1.0;
-                if (x0 >= plane && x1 < plane) cross[s] -= 1.0;
-            }
-            /* reaction next to catalytic faces of the current cell */
-            int cx = cell(x1), cy = cell(y1);
-            if (cx >= 0 && cx < nx && cy >= 0 && cy < ny && type[(size_t)cy * nx + cx] == 0) {
-                for (int d = 0; d < 4; ++d) {
-                    int sx = cx + DX[d], sy = cy + DY[d];
-                    if (sx < 0 || sx >= nx || sy < 0 || sy >= ny) continue;
-                    int ty = type[(size_t)sy * nx + sx];
-                    int src = ty == 2 ? 0 : (ty == 3 && ns == 3 ? 1 : -1);
-                    if (src != sp[j]) continue;
-                    double dist = d == 0 ? cx + 0.5 - x1 : d == 1 ? cy + 0.5 - y1
-                                : d == 2 ? x1 - (cx - 0.5) : y1 - (cy - 0.5);
-                    if (dist >= zone) continue;
-                    double p = k[(size_t)sy * nx + sx] * rate_w * dt / zone;
-                    if (unif(&r) < p) {
-                        sp[j] = (uint8_t)(src + 1);
-                        break;
-                    }
-                }
-            }
-            if (x1 >= nx - 0.5) { /* left through the outlet */
+            int ds = 0, s = sp[j];
+            int gone = move_particle(&g, ns, seed, pid[j], (uint64_t)t, dt, step_len, zone, rate_w,
+                                     buf_hi, plane, wall_mode, &px[j], &py[j], &sp[j], &ds);
+            if (measuring) cross[s] += ds;
+            if (gone) { /* left through the outlet */
                 --np;
-                px[j] = px[np]; py[j] = py[np]; sp[j] = sp[np];
+                px[j] = px[np]; py[j] = py[np]; sp[j] = sp[np]; pid[j] = pid[np];
                 continue;
             }
-            px[j] = x1;
-            py[j] = y1;
             ++j;
         }
     }
@@ -242,5 +281,25 @@ int rwpt_run(int nx, int ny, int ns, const uint8_t *type, const double *ux, cons
     free(px);
     free(py);
     free(sp);
+    free(pid);
     return status;
+}
+
+/* Trajectory mode: advance np given particles (ids, positions, species) by
+ * steps t0 .. t0+steps-1 with no insertion and no removal (a particle past
+ * the outlet keeps moving).  Returns 0. */
+int rwpt_walk(int nx, int ny, int ns, const uint8_t *type, const double *ux, const double *uy,
+              double vel_scale, double D, const double *k, double rate_w, double dt, double zone,
+              int wall_mode, uint64_t seed, long np, const uint64_t *id, double *px, double *py,
+              uint8_t *sp, long t0, long steps)
+{
+    geom_t g = {nx, ny, type, ux, uy, k, vel_scale, 0.0};
+    double step_len = sqrt(4.0 * D * dt);
+    for (long j = 0; j < np; ++j)
+        for (long t = t0; t < t0 + steps; ++t) {
+            int ds;
+            move_particle(&g, ns, seed, id[j], (uint64_t)t, dt, step_len, zone, rate_w, -0.5,
+                          nx + 10.0, wall_mode, &px[j], &py[j], &sp[j], &ds);
+        }
+    return 0;
 }

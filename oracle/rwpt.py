@@ -33,6 +33,9 @@ def lib():
         _lib.rwpt_run.restype = i
         _lib.rwpt_run.argtypes = [i, i, i, p, p, p, d, d, p, d, d, d, d, i, l, l,
                                   ctypes.c_uint64, l, i, p]
+        _lib.rwpt_walk.restype = i
+        _lib.rwpt_walk.argtypes = [i, i, i, p, p, p, d, d, p, d, d, d, i, ctypes.c_uint64, l,
+                                   p, p, p, p, l, l]
     return _lib
 
 
@@ -72,3 +75,24 @@ def efficiency_batches(node_type, ux, uy, k, nspecies, D, batches=8, seed=1, **k
         eps.append(n[-1] / n.sum())
     eps = np.array(eps)
     return eps.mean(), eps.std(ddof=1) / np.sqrt(len(eps)), eps
+
+
+def walk(node_type, ux, uy, k, nspecies, D, ids, x, y, species, t0, steps, *, vel_scale=1.0,
+         rate_w=1.0 / 6.0, dt=0.5, zone=1.0, wall_mode=1, seed=1):
+    """Trajectory mode: advance the given particles (ids uint64, positions,
+    species) by steps t0 .. t0+steps-1, no insertion or removal.  Returns new
+    (x, y, species) arrays."""
+    t = np.ascontiguousarray(node_type, dtype=np.uint8)
+    ny, nx = t.shape
+    ux = np.ascontiguousarray(ux, dtype=np.float64)
+    uy = np.ascontiguousarray(uy, dtype=np.float64)
+    k = np.ascontiguousarray(k, dtype=np.float64)
+    ids = np.ascontiguousarray(ids, dtype=np.uint64)
+    x = np.array(x, dtype=np.float64)
+    y = np.array(y, dtype=np.float64)
+    sp = np.array(species, dtype=np.uint8)
+    lib().rwpt_walk(nx, ny, nspecies, t.ctypes.data, ux.ctypes.data, uy.ctypes.data, vel_scale,
+                    D, k.ctypes.data, rate_w, dt, zone, int(wall_mode), int(seed), len(ids),
+                    ids.ctypes.data, x.ctypes.data, y.ctypes.data, sp.ctypes.data, int(t0),
+                    int(steps))
+    return x, y, sp

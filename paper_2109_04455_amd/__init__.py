@@ -14,7 +14,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import Lbf3Params, LbfParams
+from ._lib import Lbf3Params, LbfParams, LbfRwParams
 
 __all__ = ["LbfError", "LbfNotConverged", "Context", "Batch", "params", "lib", "probe_copy",
            "workspace_tensor"]
@@ -398,6 +398,93 @@ class Context3D:
     def time_flow_steps(self, nsteps):
         ms = ctypes.c_double()
         self._call("lbf3_time_flow_steps", int(nsteps), ctypes.byref(ms))
+        return ms.value
+
+
+def rw_params(nx, ny, *, nspecies=2, D=0.05, dt=0.5, zone=1.0, rate_w=1.0 / 6.0, density=10.0,
+              vel_scale=1.0, xf=-1, wall_mode=1, seed=1, capacity=None) -> LbfRwParams:
+    p = LbfRwParams()
+    _check(lib().lbf_rw_params_default(ctypes.byref(p), nx, ny))
+    p.nspecies, p.D, p.dt, p.zone, p.rate_w = nspecies, D, dt, zone, rate_w
+    p.density, p.vel_scale, p.xf, p.wall_mode, p.seed = density, vel_scale, xf, wall_mode, seed
+    p.capacity = int(capacity) if capacity else int(density * 1.5 * nx * ny) + 4096
+    return p
+
+
+class RandomWalk:
+    """GPU random-walk particle tracker on a 2D lattice geometry and flow."""
+
+    def __init__(self, p: LbfRwParams, device="cuda", stream=None):
+        self.p = p
+        self.device = torch.device(device)
+        h = ctypes.c_void_p()
+        st = lib().lbf_rw_create(ctypes.byref(p), ctypes.byref(h))
+        self._h = h
+        if st != _lib.OK:
+            msg = lib().lbf_rw_last_error(h).decode()
+            lib().lbf_rw_destroy(h)
+            self._h = None
+            raise LbfError(st, f"lbf_rw_create: {msg}")
+        nbytes = ctypes.c_size_t()
+        self._call("lbf_rw_workspace_bytes", ctypes.byref(nbytes))
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._ws, ptr = workspace_tensor(nbytes.value, self.device)
+        self._call("lbf_rw_bind", ctypes.c_void_p(ptr), nbytes.value, _stream_handle(self.stream))
+
+    def _call(self, name, *args):
+        st = getattr(lib(), name)(self._h, *args)
+        if st != _lib.OK:
+            raise LbfError(st, f"{name}: {lib().lbf_status_str(st).decode()}: "
+                               f"{lib().lbf_rw_last_error(self._h).decode()}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            torch.cuda.synchronize(self.device)
+            lib().lbf_rw_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_fields(self, node_type, ux, uy, k):
+        ts = [torch.as_tensor(node_type).to(self.device, torch.uint8).contiguous()]
+        ts += [torch.as_tensor(a).to(self.device, torch.float64).contiguous() for a in (ux, uy, k)]
+        with torch.cuda.stream(self.stream):
+            self._call("lbf_rw_set_fields", *[ctypes.c_void_p(t.data_ptr()) for t in ts])
+        torch.cuda.synchronize(self.device)
+
+    def fill(self):
+        self._call("lbf_rw_fill")
+
+    def run(self, nsteps, measure=False):
+        self._call("lbf_rw_run", int(nsteps), int(bool(measure)))
+
+    def counts(self):
+        """(N[ns] net crossings per unit time, particles held, measured steps)."""
+        n = (ctypes.c_double * 3)()
+        np_, steps = ctypes.c_long(), ctypes.c_long()
+        self._call("lbf_rw_counts", n, ctypes.byref(np_), ctypes.byref(steps))
+        return np.array(n[: self.p.nspecies]), np_.value, steps.value
+
+    def walk(self, ids, x, y, species, t0, steps):
+        """Trajectory mode on device copies; returns (x, y, species) tensors."""
+        ids = torch.as_tensor(np.asarray(ids, dtype=np.uint64).view(np.int64)).to(self.device)
+        x = torch.as_tensor(x, dtype=torch.float64).to(self.device).clone()
+        y = torch.as_tensor(y, dtype=torch.float64).to(self.device).clone()
+        sp = torch.as_tensor(species, dtype=torch.uint8).to(self.device).clone()
+        with torch.cuda.stream(self.stream):
+            self._call("lbf_rw_walk", int(x.numel()), ctypes.c_void_p(ids.data_ptr()),
+                       ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                       ctypes.c_void_p(sp.data_ptr()), int(t0), int(steps))
+        torch.cuda.synchronize(self.device)
+        return x, y, sp
+
+    def time_steps(self, nsteps, measure=False):
+        ms = ctypes.c_double()
+        self._call("lbf_rw_time_steps", int(nsteps), int(bool(measure)), ctypes.byref(ms))
         return ms.value
 
 

@@ -39,6 +39,16 @@ class Lbf3Params(ctypes.Structure):
     ]
 
 
+class LbfRwParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nspecies", ctypes.c_int),
+        ("xf", ctypes.c_int), ("wall_mode", ctypes.c_int),
+        ("D", ctypes.c_double), ("dt", ctypes.c_double), ("zone", ctypes.c_double),
+        ("rate_w", ctypes.c_double), ("density", ctypes.c_double),
+        ("vel_scale", ctypes.c_double), ("seed", ctypes.c_uint64), ("capacity", ctypes.c_long),
+    ]
+
+
 # name -> (restype, argtypes)
 _P, _I, _L, _D, _S = ctypes.c_void_p, ctypes.c_int, ctypes.c_long, ctypes.c_double, ctypes.c_size_t
 _PP = ctypes.POINTER(LbfParams)
@@ -107,6 +117,19 @@ SIGNATURES = {
     "lbf3_time_flow_steps": (_I, [_P, _L, _PD]),
     "lbf3_last_error": (ctypes.c_char_p, [_P]),
     "lbf3_destroy": (None, [_P]),
+    # random-walk tracker (include/lbf_rw.h)
+    "lbf_rw_params_default": (_I, [ctypes.POINTER(LbfRwParams), _I, _I]),
+    "lbf_rw_create": (_I, [ctypes.POINTER(LbfRwParams), ctypes.POINTER(_P)]),
+    "lbf_rw_workspace_bytes": (_I, [_P, _PS]),
+    "lbf_rw_bind": (_I, [_P, _P, _S, _P]),
+    "lbf_rw_set_fields": (_I, [_P, _P, _P, _P, _P]),
+    "lbf_rw_fill": (_I, [_P]),
+    "lbf_rw_run": (_I, [_P, _L, _I]),
+    "lbf_rw_counts": (_I, [_P, _PD, _PL, _PL]),
+    "lbf_rw_walk": (_I, [_P, _L, _P, _P, _P, _P, _L, _L]),
+    "lbf_rw_time_steps": (_I, [_P, _L, _I, _PD]),
+    "lbf_rw_last_error": (ctypes.c_char_p, [_P]),
+    "lbf_rw_destroy": (None, [_P]),
 }
 
 _lib = None

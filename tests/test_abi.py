@@ -9,14 +9,14 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("lbf.h", "lbf3d.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("lbf.h", "lbf3d.h", "lbf_rw.h")]
 
 
 def _declared():
     names = set()
     for h in HEADERS:
         text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
-        names |= set(re.findall(r"\b(lbf3?_[a-z_0-9]+)\s*\(", text))
+        names |= set(re.findall(r"\b(lbf(?:3|_rw)?_[a-z_0-9]+)\s*\(", text))
     return sorted(names)
 
 
@@ -121,7 +121,7 @@ def _params3(L, **kw):
     ("nx", 4, "nx >= 8"), ("nz", 1, "nz >= 2"), ("real_bytes", 2, "real_bytes"),
     ("nspecies", 1, "nspecies"), ("tau_f", 0.5, "tau_f"), ("tau_g", 0.2, "tau_g"),
     ("force_x", 0.1, "force_x"), ("vel_scale", -1.0, "vel_scale"), ("flux_col", 39, "flux_col"),
-    ("tile_x", 100, "tile_x"), ("tile_y", 5, "tile_x"),
+    ("tile_x", 100, "tile_x"), ("tile_y", 20, "tile_x"),
 ])
 def test_3d_invalid_parameters_rejected(L, field, value, needle):
     h = ctypes.c_void_p()
