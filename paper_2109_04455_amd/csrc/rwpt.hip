@@ -59,44 +59,59 @@ __device__ __forceinline__ bool solid(const Field &f, int cx, int cy)
 
 __device__ __forceinline__ int cell_of(double p) { return (int)floor(p + 0.5); }
 
-// Bilinear interpolation of a nodal field; in wall_mode 1 a solid corner takes
-// minus the mean of its fluid neighbours along the cell edges (or minus the
-// diagonal fluid corner), so the interpolant is zero on the half-way wall.
-__device__ double interp(const Field &f, const double *u, double px, double py)
+// Bilinear interpolation of the two velocity components at (px, py); in
+// wall_mode 1 a solid corner takes minus the mean of its fluid neighbours
+// along the cell edges (or minus the diagonal fluid corner), so the
+// interpolant is zero on the half-way wall.  Corner classification is shared
+// by both components.
+__device__ void interp2(const Field &f, double px, double py, double &uo, double &vo)
 {
     const int x0 = (int)floor(px), y0 = (int)floor(py);
     const double fx = px - x0, fy = py - y0;
-    double v[2][2];
+    double a[2][2], b[2][2];
     bool sol[2][2];
+#pragma unroll
     for (int j = 0; j < 2; ++j)
+#pragma unroll
         for (int i = 0; i < 2; ++i) {
             const int cx = x0 + i, cy = y0 + j;
             sol[j][i] = solid(f, cx, cy);
-            double val = 0.0;
-            if (!sol[j][i] && cy >= 0 && cy < f.ny) {
+            a[j][i] = b[j][i] = 0.0;
+            if (!sol[j][i]) {
                 const int xc = cx < 0 ? 0 : (cx >= f.nx ? f.nx - 1 : cx);
-                val = u[(size_t)cy * f.nx + xc];
+                const size_t id = (size_t)cy * f.nx + xc;
+                a[j][i] = f.ux[id];
+                b[j][i] = f.uy[id];
             }
-            v[j][i] = val;
         }
     if (f.wall_mode == 1) {
-        double w[2][2];
+        double wa[2][2], wb[2][2];
+#pragma unroll
         for (int j = 0; j < 2; ++j)
+#pragma unroll
             for (int i = 0; i < 2; ++i) {
-                w[j][i] = v[j][i];
+                wa[j][i] = a[j][i];
+                wb[j][i] = b[j][i];
                 if (!sol[j][i]) continue;
-                double s = 0.0;
+                double sa = 0.0, sb = 0.0;
                 int n = 0;
-                if (!sol[j][1 - i]) { s -= v[j][1 - i]; ++n; }
-                if (!sol[1 - j][i]) { s -= v[1 - j][i]; ++n; }
-                if (n == 0 && !sol[1 - j][1 - i]) { s -= v[1 - j][1 - i]; n = 1; }
-                w[j][i] = n ? s / n : 0.0;
+                if (!sol[j][1 - i]) { sa -= a[j][1 - i]; sb -= b[j][1 - i]; ++n; }
+                if (!sol[1 - j][i]) { sa -= a[1 - j][i]; sb -= b[1 - j][i]; ++n; }
+                if (n == 0 && !sol[1 - j][1 - i]) { sa -= a[1 - j][1 - i]; sb -= b[1 - j][1 - i]; n = 1; }
+                wa[j][i] = n ? sa / n : 0.0;
+                wb[j][i] = n ? sb / n : 0.0;
             }
+#pragma unroll
         for (int j = 0; j < 2; ++j)
-            for (int i = 0; i < 2; ++i) v[j][i] = w[j][i];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                a[j][i] = wa[j][i];
+                b[j][i] = wb[j][i];
+            }
     }
-    return (1 - fx) * (1 - fy) * v[0][0] + fx * (1 - fy) * v[0][1] + (1 - fx) * fy * v[1][0] +
-           fx * fy * v[1][1];
+    const double c00 = (1 - fx) * (1 - fy), c01 = fx * (1 - fy), c10 = (1 - fx) * fy, c11 = fx * fy;
+    uo = c00 * a[0][0] + c01 * a[0][1] + c10 * a[1][0] + c11 * a[1][1];
+    vo = c00 * b[0][0] + c01 * b[0][1] + c10 * b[1][0] + c11 * b[1][1];
 }
 
 // Specular reflection of the move (px, py) -> (qx, qy) at the faces of solid
@@ -130,7 +145,10 @@ __device__ int move(const Field &f, uint64_t id, uint64_t t, double buf_hi, doub
                     double &x, double &y, uint8_t &s)
 {
     const double x0 = x, y0 = y;
-    const double u = f.vs * interp(f, f.ux, x0, y0), v = f.vs * interp(f, f.uy, x0, y0);
+    double u, v;
+    interp2(f, x0, y0, u, v);
+    u *= f.vs;
+    v *= f.vs;
     double sn, cs;
     sincos(2.0 * M_PI * draw(f.seed, id, t, 0), &sn, &cs);
     double x1 = x0 + u * f.dt + f.len * cs;
@@ -179,59 +197,75 @@ struct Scalars {
 };
 
 // ---- order-preserving chunked scans ----------------------------------------
-// Block b owns items [b*chunk, (b+1)*chunk), thread j of the block a
-// contiguous sub-range of it; counts are summed per thread, scanned in LDS,
-// and the block totals are scanned by one block.
+// Block b owns items [b*chunk, (b+1)*chunk) (chunk a multiple of the block
+// size) and walks them in tiles of SCAN_THREADS consecutive items, thread j
+// taking item j of each tile, so every access of a wavefront is coalesced.
+// Inside a tile the rank of an item comes from a wavefront ballot plus the
+// counts of the lower wavefronts; block totals are scanned by one block.
 
-__device__ __forceinline__ void chunk_range(long long n, long long &t0, long long &t1)
+__device__ __forceinline__ void chunk_bounds(long long n, long long &b0, long long &b1)
 {
-    const long long chunk = (n + SCAN_BLOCKS - 1) / SCAN_BLOCKS;
-    const long long sub = (chunk + SCAN_THREADS - 1) / SCAN_THREADS;
-    const long long b0 = (long long)blockIdx.x * chunk, b1 = min(n, b0 + chunk);
-    t0 = min(b1, b0 + (long long)threadIdx.x * sub);
-    t1 = min(b1, t0 + sub);
+    long long chunk = (n + SCAN_BLOCKS - 1) / SCAN_BLOCKS;
+    chunk = (chunk + SCAN_THREADS - 1) / SCAN_THREADS * SCAN_THREADS;
+    b0 = min(n, (long long)blockIdx.x * chunk);
+    b1 = min(n, b0 + chunk);
 }
 
-// exclusive scan of v over the block; returns the block total in *total
-__device__ long long block_exscan(long long v, long long *total)
+// rank of this thread's predicate among the set predicates of the tile
+// (lower threads first); *tile_total receives the tile's count
+__device__ __forceinline__ int tile_rank(bool pred, int *tile_total)
+{
+    __shared__ int wsum[SCAN_THREADS / 64];
+    const unsigned long long m = __ballot(pred);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int in_wave = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[wave] = __popcll(m);
+    __syncthreads();
+    int below = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < SCAN_THREADS / 64; ++w) {
+        below += w < wave ? wsum[w] : 0;
+        total += wsum[w];
+    }
+    __syncthreads();
+    *tile_total = total;
+    return below + in_wave;
+}
+
+__device__ long long block_sum(long long v)
 {
     __shared__ long long sm[SCAN_THREADS];
     sm[threadIdx.x] = v;
     __syncthreads();
-    for (int off = 1; off < SCAN_THREADS; off <<= 1) {
-        const long long a = threadIdx.x >= (unsigned)off ? sm[threadIdx.x - off] : 0;
-        __syncthreads();
-        sm[threadIdx.x] += a;
+    for (int s = SCAN_THREADS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
         __syncthreads();
     }
-    const long long incl = sm[threadIdx.x];
-    *total = sm[SCAN_THREADS - 1];
+    const long long r = sm[0];
     __syncthreads();
-    return incl - v;
+    return r;
 }
 
 __device__ __forceinline__ bool alive(double x, int nx) { return x >= BUF_HI && x < nx - 0.5; }
 
 // pass 1 of the compaction: survivors per block
 __global__ __launch_bounds__(SCAN_THREADS) void k_count_alive(Parts p, const Scalars *sc, int nx,
-                                                               long long *block_sum)
+                                                               long long *block_total)
 {
-    long long t0, t1;
-    chunk_range(sc->n_cur, t0, t1);
+    long long b0, b1;
+    chunk_bounds(sc->n_cur, b0, b1);
     long long c = 0;
-    for (long long i = t0; i < t1; ++i) c += alive(p.x[i], nx);
-    long long total;
-    block_exscan(c, &total);
-    if (threadIdx.x == 0) block_sum[blockIdx.x] = total;
+    for (long long i = b0 + threadIdx.x; i < b1; i += SCAN_THREADS) c += alive(p.x[i], nx);
+    const long long total = block_sum(c);
+    if (threadIdx.x == 0) block_total[blockIdx.x] = total;
 }
 
-// scan of the block totals (one block of SCAN_BLOCKS threads); for the
-// compaction also sets n_alive
-__global__ __launch_bounds__(SCAN_BLOCKS) void k_scan_top(const long long *block_sum,
+// scan of the block totals (one block of SCAN_BLOCKS threads)
+__global__ __launch_bounds__(SCAN_BLOCKS) void k_scan_top(const long long *block_total,
                                                           long long *block_off, long long *total_out)
 {
     __shared__ long long sm[SCAN_BLOCKS];
-    const long long v = block_sum[threadIdx.x];
+    const long long v = block_total[threadIdx.x];
     sm[threadIdx.x] = v;
     __syncthreads();
     for (int off = 1; off < SCAN_BLOCKS; off <<= 1) {
@@ -248,20 +282,23 @@ __global__ __launch_bounds__(SCAN_BLOCKS) void k_scan_top(const long long *block
 __global__ __launch_bounds__(SCAN_THREADS) void k_compact(Parts src, Parts dst, const Scalars *sc,
                                                            int nx, const long long *block_off)
 {
-    long long t0, t1;
-    chunk_range(sc->n_cur, t0, t1);
-    long long c = 0;
-    for (long long i = t0; i < t1; ++i) c += alive(src.x[i], nx);
-    long long total;
-    long long o = block_off[blockIdx.x] + block_exscan(c, &total);
-    for (long long i = t0; i < t1; ++i) {
-        const double x = src.x[i];
-        if (!alive(x, nx)) continue;
-        dst.x[o] = x;
-        dst.y[o] = src.y[i];
-        dst.sp[o] = src.sp[i];
-        dst.id[o] = src.id[i];
-        ++o;
+    long long b0, b1;
+    chunk_bounds(sc->n_cur, b0, b1);
+    long long base = block_off[blockIdx.x];
+    for (long long t = b0; t < b1; t += SCAN_THREADS) {
+        const long long i = t + threadIdx.x;
+        const double x = i < b1 ? src.x[i] : 0.0;
+        const bool a = i < b1 && alive(x, nx);
+        int tile_total;
+        const int r = tile_rank(a, &tile_total);
+        if (a) {
+            const long long o = base + r;
+            dst.x[o] = x;
+            dst.y[o] = src.y[i];
+            dst.sp[o] = src.sp[i];
+            dst.id[o] = src.id[i];
+        }
+        base += tile_total;
     }
 }
 
@@ -335,15 +372,32 @@ __global__ void k_fill_count(Field f, double density, int *counts)
 }
 
 __global__ __launch_bounds__(SCAN_THREADS) void k_fill_sum(const int *counts, long long ncell,
-                                                            long long *block_sum)
+                                                            long long *block_total)
 {
-    long long t0, t1;
-    chunk_range(ncell, t0, t1);
+    long long b0, b1;
+    chunk_bounds(ncell, b0, b1);
     long long c = 0;
-    for (long long i = t0; i < t1; ++i) c += counts[i];
-    long long total;
-    block_exscan(c, &total);
-    if (threadIdx.x == 0) block_sum[blockIdx.x] = total;
+    for (long long i = b0 + threadIdx.x; i < b1; i += SCAN_THREADS) c += counts[i];
+    const long long total = block_sum(c);
+    if (threadIdx.x == 0) block_total[blockIdx.x] = total;
+}
+
+// exclusive scan over the block (LDS); *total receives the block sum
+__device__ long long block_exscan(long long v, long long *total)
+{
+    __shared__ long long sm[SCAN_THREADS];
+    sm[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < SCAN_THREADS; off <<= 1) {
+        const long long a = threadIdx.x >= (unsigned)off ? sm[threadIdx.x - off] : 0;
+        __syncthreads();
+        sm[threadIdx.x] += a;
+        __syncthreads();
+    }
+    const long long incl = sm[threadIdx.x];
+    *total = sm[SCAN_THREADS - 1];
+    __syncthreads();
+    return incl - v;
 }
 
 __global__ __launch_bounds__(SCAN_THREADS) void k_fill_place(Field f, const int *counts,
@@ -351,14 +405,14 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_fill_place(Field f, const int 
                                                               long long capacity, Scalars *sc)
 {
     const long long ncell = (long long)f.nx * f.ny;
-    long long t0, t1;
-    chunk_range(ncell, t0, t1);
-    long long c = 0;
-    for (long long i = t0; i < t1; ++i) c += counts[i];
-    long long total;
-    long long o = block_off[blockIdx.x] + block_exscan(c, &total);
-    for (long long cidx = t0; cidx < t1; ++cidx) {
-        const int n = counts[cidx];
+    long long b0, b1;
+    chunk_bounds(ncell, b0, b1);
+    long long base = block_off[blockIdx.x];
+    for (long long t = b0; t < b1; t += SCAN_THREADS) {
+        const long long cidx = t + threadIdx.x;
+        const int n = cidx < b1 ? counts[cidx] : 0;
+        long long tile_total;
+        long long o = base + block_exscan(n, &tile_total);
         const int cx = (int)(cidx % f.nx), cy = (int)(cidx / f.nx);
         for (int j = 0; j < n; ++j, ++o) {
             if (o >= capacity) {
@@ -371,6 +425,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_fill_place(Field f, const int 
             dst.sp[o] = 0;
             dst.id[o] = id;
         }
+        base += tile_total;
     }
 }
 
