@@ -134,17 +134,17 @@ __global__ __launch_bounds__(1024) void k_flow_step3(FlowArgs3<Real> a)
     const int y = row % g.ny, z = row / g.ny;
     const size_t P = g.plane;
     Acc h[19];
-    h[0] = Acc(ld<NT>(a.src + id));
+    h[0] = Acc(ld<NT>(a.src + pidx<19>(id, 0)));
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
         const int o = opp19(i);
         if ((m >> (o - 1)) & 1u) {
-            h[i] = Acc(ld<NT>(a.src + (size_t)o * P + id));  // half-way bounce-back
+            h[i] = Acc(ld<NT>(a.src + pidx<19>(id, o)));  // half-way bounce-back
         } else {
             int sx = x - CX[i];
             sx = sx < 0 ? sx + g.nx : (sx >= g.nx ? sx - g.nx : sx);
             const size_t sid = (size_t)row_of(g, y, z, -CY[i], -CZ[i]) * g.nxp + sx;
-            h[i] = Acc(ld<NT>(a.src + (size_t)i * P + sid));
+            h[i] = Acc(ld<NT>(a.src + pidx<19>(sid, i)));
         }
     }
     Acc u[3];
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(1024) void k_flow_step3(FlowArgs3<Real> a)
         a.u[2 * P + id] = Real(u[2]);
     }
 #pragma unroll
-    for (int i = 0; i < 19; ++i) st<NT>(a.dst + (size_t)i * P + id, Real(h[i]));
+    for (int i = 0; i < 19; ++i) st<NT>(a.dst + pidx<19>(id, i), Real(h[i]));
 }
 
 // Rest fluid (h = 0) and its first collision; solids hold zeros.
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(1024) void k_flow_init3(FlowArgs3<Real> a)
     const size_t id = (size_t)row * g.nxp + x;
     const size_t P = g.plane;
     if (a.mask19[id] & MASK19_SOLID) {
-        for (int i = 0; i < 19; ++i) a.dst[(size_t)i * P + id] = Real(0);
+        for (int i = 0; i < 19; ++i) a.dst[pidx<19>(id, i)] = Real(0);
         for (int c = 0; c < 3; ++c) a.u[(size_t)c * P + id] = Real(0);
         return;
     }
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(1024) void k_flow_init3(FlowArgs3<Real> a)
     double u[3];
     collide19(h, a.omega, a.fx, u);
     for (int c = 0; c < 3; ++c) a.u[(size_t)c * P + id] = Real(u[c]);
-    for (int i = 0; i < 19; ++i) a.dst[(size_t)i * P + id] = Real(h[i]);
+    for (int i = 0; i < 19; ++i) a.dst[pidx<19>(id, i)] = Real(h[i]);
 }
 
 // max |u - uprev| and max |u| over fluid nodes (per-block partials), then
@@ -282,39 +282,39 @@ __global__ void k_pad3(const Real *src, Real *dst, const uint8_t *type_pad, Geo 
 }
 
 // ------------------------------------------------------------------- ADR ----
-// Gather the pre-collision shifted populations of one species at node
-// (x, row) from the previous post-collision lattice `src` (base of the
-// species).  Directions 1..6 = +x, -x, +y, -y, +z, -z.
-template <typename Real, typename Acc, bool NT>
-__device__ __forceinline__ void pull7(const Real *__restrict__ src, size_t P, size_t id, int x,
+// Gather the pre-collision shifted populations of one species (populations
+// q0 .. q0+6 of a lattice of NQ populations) at node id = (x, row) from the
+// previous post-collision lattice.  Directions 1..6 = +x, -x, +y, -y, +z, -z.
+template <typename Real, typename Acc, bool NT, int NQ>
+__device__ __forceinline__ void pull7(const Real *__restrict__ lat, int q0, size_t id, int x,
                                       int nx, const size_t (&nb)[7], unsigned m, bool species_a,
                                       Acc inlet_e, Acc (&h)[7])
 {
-    h[0] = Acc(ld<NT>(src + id));
+    auto at = [&](size_t node, int d) { return Acc(ld<NT>(lat + pidx<NQ>(node, q0 + d))); };
+    h[0] = at(id, 0);
     // +x arrives from x - 1
     if (x == 0)
-        h[1] = species_a ? inlet_e - Acc(ld<NT>(src + 2 * P + id)) : Acc(ld<NT>(src + 2 * P + id));
+        h[1] = species_a ? inlet_e - at(id, 2) : at(id, 2);
     else if (m & 2u)
-        h[1] = Acc(ld<NT>(src + 2 * P + id));
+        h[1] = at(id, 2);
     else
-        h[1] = Acc(ld<NT>(src + P + nb[2]));
+        h[1] = at(nb[2], 1);
     // -x arrives from x + 1
     if (x == nx - 1) {
         Acc sum = Acc(0);
 #pragma unroll
-        for (int j = 0; j < 7; ++j) sum += Acc(ld<NT>(src + (size_t)j * P + id));
-        h[2] = Acc(2) * w7<Acc>(2) * sum - Acc(ld<NT>(src + P + id));
+        for (int j = 0; j < 7; ++j) sum += at(id, j);
+        h[2] = Acc(2) * w7<Acc>(2) * sum - at(id, 1);
     } else if (m & 1u) {
-        h[2] = Acc(ld<NT>(src + P + id));
+        h[2] = at(id, 1);
     } else {
-        h[2] = Acc(ld<NT>(src + 2 * P + nb[1]));
+        h[2] = at(nb[1], 2);
     }
     // +-y, +-z: periodic; bounce-back at solid neighbours
 #pragma unroll
     for (int d = 3; d < 7; ++d) {
         const int o = d & 1 ? d + 1 : d - 1;
-        h[d] = (m >> (o - 1)) & 1u ? Acc(ld<NT>(src + (size_t)o * P + id))
-                                   : Acc(ld<NT>(src + (size_t)d * P + nb[o]));
+        h[d] = (m >> (o - 1)) & 1u ? at(id, o) : at(nb[o], d);
     }
 }
 
@@ -401,12 +401,12 @@ __global__ __launch_bounds__(1024) void k_adr_step3(AdrArgs3<Real> a)
     Acc h[S][7];
 #pragma unroll
     for (int s = 0; s < S; ++s)
-        pull7<Real, Acc, NT>(a.src + (size_t)s * 7 * P, P, id, x, g.nx, nb, m, s == 0, inlet_e, h[s]);
+        pull7<Real, Acc, NT, 7 * S>(a.src, 7 * s, id, x, g.nx, nb, m, s == 0, inlet_e, h[s]);
     collide_react7<Real, Acc, S>(a, m, nb, Acc(a.ua[id]), Acc(a.ua[P + id]), Acc(a.ua[2 * P + id]), h);
 #pragma unroll
     for (int s = 0; s < S; ++s)
 #pragma unroll
-        for (int i = 0; i < 7; ++i) st<NT>(a.dst + (size_t)(s * 7 + i) * P + id, Real(h[s][i]));
+        for (int i = 0; i < 7; ++i) st<NT>(a.dst + pidx<7 * S>(id, 7 * s + i), Real(h[s][i]));
 }
 
 // A at equilibrium with C = c_in, B = C = 0, then the first collision.
@@ -422,7 +422,7 @@ __global__ __launch_bounds__(1024) void k_adr_init3(AdrArgs3<Real> a)
     const unsigned m = a.mask7[id];
     if (m == MASK7_SOLID) {
         for (int s = 0; s < S; ++s)
-            for (int i = 0; i < 7; ++i) a.dst[(size_t)(s * 7 + i) * P + id] = Real(0);
+            for (int i = 0; i < 7; ++i) a.dst[pidx<7 * S>(id, 7 * s + i)] = Real(0);
         return;
     }
     const int y = row % g.ny, z = row / g.ny;
@@ -440,7 +440,7 @@ __global__ __launch_bounds__(1024) void k_adr_init3(AdrArgs3<Real> a)
     }
     collide_react7<Real, double, S>(a, m, nb, u, v, w, h);
     for (int s = 0; s < S; ++s)
-        for (int i = 0; i < 7; ++i) a.dst[(size_t)(s * 7 + i) * P + id] = Real(h[s][i]);
+        for (int i = 0; i < 7; ++i) a.dst[pidx<7 * S>(id, 7 * s + i)] = Real(h[s][i]);
 }
 
 // Outlet fluxes through the face xf + 1/2 and the inlet flux of A, from the
@@ -453,17 +453,16 @@ __global__ __launch_bounds__(1024) void k_flux3(AdrArgs3<Real> a, int xf, double
 {
     __shared__ double sm[4][1024];
     const Geo &g = a.g;
-    const size_t P = g.plane;
     double acc[4] = {0, 0, 0, 0};
     const int rows = g.ny * g.nz;
     for (int r = threadIdx.x; r < rows; r += blockDim.x) {
         const size_t i0 = (size_t)r * g.nxp;
         if (a.mask7[i0 + xf] != MASK7_SOLID && a.mask7[i0 + xf + 1] != MASK7_SOLID)
             for (int s = 0; s < S; ++s)
-                acc[s] += (double)a.src[(size_t)(s * 7 + 1) * P + i0 + xf] -
-                          (double)a.src[(size_t)(s * 7 + 2) * P + i0 + xf + 1];
+                acc[s] += (double)a.src[pidx<7 * S>(i0 + xf, 7 * s + 1)] -
+                          (double)a.src[pidx<7 * S>(i0 + xf + 1, 7 * s + 2)];
         if (a.mask7[i0] != MASK7_SOLID)
-            acc[3] += 2.0 * 0.125 * (a.cin - a.cref) - 2.0 * (double)a.src[2 * P + i0];
+            acc[3] += 2.0 * 0.125 * (a.cin - a.cref) - 2.0 * (double)a.src[pidx<7 * S>(i0, 2)];
     }
     for (int s = 0; s < 4; ++s) sm[s][threadIdx.x] = acc[s];
     __syncthreads();
@@ -493,8 +492,8 @@ __global__ __launch_bounds__(1024) void k_conc3(AdrArgs3<Real> a, int species, R
         neighbours7(g, x, y, z, nb);
         double h[7];
         const double inlet_e = 2.0 * 0.125 * (a.cin - a.cref);
-        pull7<Real, double, false>(a.src + (size_t)species * 7 * g.plane, g.plane, id, x, g.nx, nb,
-                                   m, species == 0, inlet_e, h);
+        pull7<Real, double, false, 7 * S>(a.src, 7 * species, id, x, g.nx, nb, m, species == 0,
+                                          inlet_e, h);
         c = species == 0 ? a.cref : 0.0;
         for (int i = 0; i < 7; ++i) c += h[i];
     }
@@ -521,8 +520,7 @@ __global__ __launch_bounds__(256) void k_totals3(AdrArgs3<Real> a, double *parti
         neighbours7(g, x, y, z, nb);
         for (int s = 0; s < S; ++s) {
             double h[7];
-            pull7<Real, double, false>(a.src + (size_t)s * 7 * g.plane, g.plane, id, x, g.nx, nb, m,
-                                       s == 0, inlet_e, h);
+            pull7<Real, double, false, 7 * S>(a.src, 7 * s, id, x, g.nx, nb, m, s == 0, inlet_e, h);
             double c = s == 0 ? a.cref : 0.0;
             for (int j = 0; j < 7; ++j) c += h[j];
             acc[s] += c;

@@ -1,7 +1,9 @@
 // Internal declarations and per-node device code of the 3D path: D3Q19 flow
-// with a body force and D3Q7 ADR with link reactions.  Lattice nodes are
-// stored row by row, a row being one (y, z) line of nxp >= nx nodes (x
-// fastest), rows ordered row = z * ny + y; plane = nxp * ny * nz.
+// with a body force and D3Q7 ADR with link reactions.  Nodes are numbered row
+// by row, a row being one (y, z) line of nxp >= nx nodes (x fastest), rows
+// ordered row = z * ny + y; plane = nxp * ny * nz.  Node fields (masks,
+// velocities) are plain [plane] arrays; populations use the segment layout
+// of pidx below.
 #pragma once
 
 #include "lbf3d.h"
@@ -44,7 +46,7 @@ struct FlowArgs3 {
 
 template <typename Real>
 struct AdrArgs3 {
-    const Real *src;    // post-collision state of the previous step [S][7][plane]
+    const Real *src;    // post-collision state of the previous step (7 S populations)
     Real *dst;
     const Real *ua;     // [3][plane] ADR velocity
     const uint16_t *mask7;
@@ -56,6 +58,20 @@ struct AdrArgs3 {
     double cref;        // storage shift of species A (g - w_i cref)
     Launch L;
 };
+
+// Population layout: the NQ populations of 64 consecutive nodes of a row are
+// stored together (rows are padded to a multiple of 64 nodes, so a segment
+// never straddles two rows).  A wavefront then finds all the populations of
+// its 64 nodes in one block of NQ * 64 elements instead of in NQ planes far
+// apart, which keeps the many row streams of a 3D stencil on few HBM pages.
+constexpr int SEG = 64;
+static_assert(ROW_ALIGN % SEG == 0, "segments must not straddle rows");
+
+template <int NQ>
+__device__ __forceinline__ size_t pidx(size_t node, int q)
+{
+    return ((node / SEG) * NQ + (size_t)q) * SEG + node % SEG;
+}
 
 // Row index of (y + dy, z + dz), periodic in y and z (|dy|, |dz| <= 1).
 __device__ __forceinline__ int row_of(const Geo &g, int y, int z, int dy, int dz)
