@@ -77,6 +77,19 @@ def test_invalid_parameters_rejected(L, field, value, needle):
     assert st == -1 and needle in msg
 
 
+def test_lattice_size_limits(L):
+    # 2^32 nodes is the largest 2D lattice; 3D stops at 2e9 nodes
+    st, msg = _create(L, _params(L, nx=70000, ny=70000))
+    assert st == -1 and "too large" in msg
+    st, _ = _create(L, _params(L, nx=65536, ny=65536))
+    assert st == 0
+    h = ctypes.c_void_p()
+    st = L.lbf3_create(ctypes.byref(_params3(L, nx=2000, ny=1000, nz=1001)), ctypes.byref(h))
+    msg = L.lbf3_last_error(h).decode()
+    L.lbf3_destroy(h)
+    assert st == -1 and "too large" in msg
+
+
 def test_valid_parameters_and_workspace_arithmetic(L):
     p = _params(L, nx=100, ny=30)
     h = ctypes.c_void_p()
