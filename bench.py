@@ -122,6 +122,9 @@ def adjoint_leg(T=20000, M=200):
         out[f"{tag}_ratio"] = round(dt / fwd, 3)
         out["eps"] = eps
         out["grad_max_abs"] = float(grad.abs().max())
+    keep = c.adjoint_path(T, M)
+    out["default_path"] = "keep_trace" if keep else "recompute"
+    out["ratio"] = out["keep_trace_ratio" if keep else "recompute_ratio"]
     c.close()
     return out
 

@@ -206,8 +206,21 @@ class Context:
         return s.value
 
     # --------------------------------------------------------------- adjoint
-    def adjoint(self, T, ckpt_every=200, keep_trace=False):
-        """(eps, grad_k [ny, nx] float64 tensor) after T further steps."""
+    def adjoint_path(self, T, ckpt_every=200, budget_fraction=0.25):
+        """True (keep the whole trace: ~2x the forward) when its workspace fits
+        in budget_fraction of the free device memory, else False
+        (checkpoints + recompute: ~3x the forward, memory ~ T/ckpt_every
+        lattices)."""
+        nbytes = ctypes.c_size_t()
+        self._call("lbf_adjoint_workspace_bytes", int(T), int(ckpt_every), 1, ctypes.byref(nbytes))
+        free, _ = torch.cuda.mem_get_info(self.device)
+        return nbytes.value <= budget_fraction * free
+
+    def adjoint(self, T, ckpt_every=200, keep_trace=None):
+        """(eps, grad_k [ny, nx] float64 tensor) after T further steps.
+        keep_trace None: chosen by adjoint_path."""
+        if keep_trace is None:
+            keep_trace = self.adjoint_path(T, ckpt_every)
         nbytes = ctypes.c_size_t()
         self._call("lbf_adjoint_workspace_bytes", int(T), int(ckpt_every), int(bool(keep_trace)),
                    ctypes.byref(nbytes))

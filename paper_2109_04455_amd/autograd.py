@@ -33,12 +33,13 @@ class _Eps(torch.autograd.Function):
 class EfficiencyOfRates:
     """eps(k) over a fixed window of T ADR steps of an existing context."""
 
-    def __init__(self, ctx, node_type, T, ckpt_every=200, keep_trace=False):
+    def __init__(self, ctx, node_type, T, ckpt_every=200, keep_trace=None):
         self.ctx = ctx
         t = np.asarray(node_type)
         self.cat = np.nonzero(t >= 2)
         self.shape = t.shape
-        self.T, self.M, self.keep = int(T), int(ckpt_every), bool(keep_trace)
+        self.T, self.M = int(T), int(ckpt_every)
+        self.keep = None if keep_trace is None else bool(keep_trace)  # None: by memory
         self.start = ctx.get_state()
 
     def _run(self, k_cat):

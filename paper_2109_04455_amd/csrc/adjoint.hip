@@ -380,12 +380,17 @@ lbf_status lbf_adr_adjoint(lbf_ctx c, long T, int M, int keep, void *ws, size_t 
         e = hipMemcpyAsync(W + L.ckpt, c->ptr(c->off.g[c->gpar]), L.lattice, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return hip_fail(c, e, "checkpoint copy");
     }
+    // the last segment's trace is recorded here directly into the segment
+    // trace buffer, which the reverse sweep visits first: no recompute for it
+    const long last_a0 = (L.nseg - 1) * (long)M;
     for (long m = 1; m <= T; ++m) {
         void *tr = nullptr;
         if (keep) {
             if (m < T) tr = slot(L.trace, m);
         } else if (m % M == 0 && m < T) {
             tr = slot(L.ckpt_trace, m / M);
+        } else if (m > last_a0 && m < T) {
+            tr = slot(L.trace, m - last_a0);
         }
         e = enqueue_adr_step(c, c->gpar, s, tr);
         if (e != hipSuccess) return hip_fail(c, e, "forward step");
@@ -436,7 +441,7 @@ lbf_status lbf_adr_adjoint(lbf_ctx c, long T, int M, int keep, void *ws, size_t 
             if (e != hipSuccess) return hip_fail(c, e, "segment trace copy");
             const void *src = W + L.ckpt + (size_t)j * L.lattice;
             int r = 0;
-            for (long q = 1; q < a1 - a0; ++q) {
+            for (long q = 1; q < a1 - a0 && j < L.nseg - 1; ++q) {
                 e = forward_step(c, src, rec[r], slot(L.trace, q), s);
                 if (e != hipSuccess) return hip_fail(c, e, "recompute step");
                 src = rec[r];

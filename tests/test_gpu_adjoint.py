@@ -67,7 +67,7 @@ def test_adjoint_long_window_tends_to_steady_adjoint():
     c.flow_run(3000)
     c.adr_init()
     c.adr_run(30000, tol=0)            # converged to round-off
-    eps, grad = c.adjoint(30000, ckpt_every=1000)
+    eps, grad = c.adjoint(30000, ckpt_every=1000, keep_trace=False)
     grad = grad.cpu().numpy()
     assert abs(eps / eps_ss - 1) < 1e-10
     assert np.abs(grad - grad_ss).max() < 1e-7 * np.abs(grad_ss).max()
