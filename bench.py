@@ -400,7 +400,7 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-            "kernel": "k_adr_step<float,double,3,false,true>", "bytes_per_launch": step_bytes,
+            "kernel": "k_adr_step<float,double,3,false,true,false>", "bytes_per_launch": step_bytes,
             "bytes_per_fluid_node": per_fluid, "avg_launch_us": round(launch_s * 1e6, 3),
         },
         "eps": eps, "N": [float(v) for v in N], "inflow": inflow,

@@ -89,7 +89,11 @@ typedef struct {
                             node update computes in FP64, rounding once per store);
                             bit 5: FP32 arithmetic in the flow step only;
                             bit 6: streaming accesses even when the lattice fits
-                            the 256 MiB last-level cache (default there: cached) */
+                            the 256 MiB last-level cache (default there: cached);
+                            bit 7: 64-bit population offsets in the flow and ADR
+                            node updates (default: 32-bit offsets through buffer
+                            descriptors while the 9-plane flow lattice is below
+                            4 GiB, 64-bit beyond; results are identical) */
     int boundary;        /* 0: channel (solid rows 0 and ny-1, inlet at x = 0,
                             outlet at x = nx-1); 1: box periodic in x and y with no
                             inlet or outlet (ADR only: no flow solve, no fluxes,

@@ -26,35 +26,37 @@ __device__ __forceinline__ T w5(int i)
 }
 
 // Gather the pre-collision (shifted) populations of one species at node
-// (x, y) from the post-collision lattice `src` (base of this species).
-template <typename Real, typename Acc, bool NT>
+// (x, y) from the post-collision lattice `src` (base of this species; plane d
+// starts at src + d P).  Offsets are in bytes from src, so a choice between
+// two sources is a choice of offset (see PopBlock).
+template <typename Real, typename Acc, bool NT, bool WIDE>
 __device__ __forceinline__ void pull5(const Real *__restrict__ src, size_t P, size_t id, int x,
                                       int nx, int nxp, unsigned m, bool species_a, Acc inlet_e,
                                       Acc (&h)[5])
 {
-    h[0] = Acc(ld<NT>(src + id));
+    using Off = off_t_<WIDE>;
+    constexpr Off B = sizeof(Real);
+    const Off PB = (Off)P * B, o = (Off)id * B, RB = (Off)nxp * B;
+    const PopBlock<Real, NT, WIDE> blk(src, 5 * PB);
+    auto at = [&](Off off) { return Acc(blk.load(off)); };
+    const Off oE = o + DE * PB, oN = o + DN * PB, oW = o + DW * PB, oS = o + DS * PB;
+    h[0] = at(o);
     // E arrives from x - 1
     if (x == 0)
-        h[DE] = species_a ? inlet_e - Acc(ld<NT>(src + DW * P + id)) : Acc(ld<NT>(src + DW * P + id));
-    else if (m & BIT_W)
-        h[DE] = Acc(ld<NT>(src + DW * P + id));
+        h[DE] = species_a ? inlet_e - at(oW) : at(oW);
     else
-        h[DE] = Acc(ld<NT>(src + DE * P + id - 1));
+        h[DE] = at((m & BIT_W) ? oW : oE - B);
     // N arrives from y - 1
-    h[DN] = Acc((m & BIT_S) ? ld<NT>(src + DS * P + id) : ld<NT>(src + DN * P + id - nxp));
+    h[DN] = at((m & BIT_S) ? oS : oN - RB);
     // W arrives from x + 1
     if (x == nx - 1) {
-        const Acc sum = Acc(ld<NT>(src + id)) + Acc(ld<NT>(src + DE * P + id)) +
-                        Acc(ld<NT>(src + DN * P + id)) + Acc(ld<NT>(src + DW * P + id)) +
-                        Acc(ld<NT>(src + DS * P + id));
-        h[DW] = Acc(2) * w5<Acc>(DW) * sum - Acc(ld<NT>(src + DE * P + id));
-    } else if (m & BIT_E) {
-        h[DW] = Acc(ld<NT>(src + DE * P + id));
+        const Acc sum = at(o) + at(oE) + at(oN) + at(oW) + at(oS);
+        h[DW] = Acc(2) * w5<Acc>(DW) * sum - at(oE);
     } else {
-        h[DW] = Acc(ld<NT>(src + DW * P + id + 1));
+        h[DW] = at((m & BIT_E) ? oE : oW + B);
     }
     // S arrives from y + 1
-    h[DS] = Acc((m & BIT_N) ? ld<NT>(src + DN * P + id) : ld<NT>(src + DS * P + id + nxp));
+    h[DS] = at((m & BIT_N) ? oN : oS + RB);
 }
 
 // Gather for a box periodic in x and y (no inlet or outlet); solid
@@ -179,20 +181,25 @@ __device__ __forceinline__ void collide_react(const AdrArgs<Real> &a, size_t id,
 }
 
 // Collide + react + store for one node given its gathered populations.
-template <typename Real, typename Acc, int S, bool TRACE, bool NT>
+template <typename Real, typename Acc, int S, bool TRACE, bool NT, bool WIDE>
 __device__ __forceinline__ void collide_react_store(const AdrArgs<Real> &a, size_t id, unsigned m,
                                                     Acc (&h)[S][5])
 {
-    const size_t P = a.plane;
-    collide_react<Real, Acc, S, TRACE>(a, id, m, Acc(a.ua[id]), Acc(a.ua[P + id]), h);
+    using Off = off_t_<WIDE>;
+    constexpr Off B = sizeof(Real);
+    const Off PB = (Off)a.plane * B, o = (Off)id * B;
+    const PopBlock<Real, false, WIDE> vel(a.ua, 2 * PB);
+    collide_react<Real, Acc, S, TRACE>(a, id, m, Acc(vel.load(o)), Acc(vel.load(o + PB)), h);
 #pragma unroll
-    for (int s = 0; s < S; ++s)
+    for (int s = 0; s < S; ++s) {
+        const PopBlock<Real, NT, WIDE> out(a.dst + (size_t)s * 5 * a.plane, 5 * PB);
 #pragma unroll
-        for (int i = 0; i < 5; ++i) st<NT>(a.dst + (s * 5 + i) * P + id, Real(h[s][i]));
+        for (int i = 0; i < 5; ++i) out.store(o + i * PB, Real(h[s][i]));
+    }
 }
 
 // Full update of node (x, y): gather, collide, react, store.
-template <typename Real, typename Acc, int S, bool TRACE, bool NT>
+template <typename Real, typename Acc, int S, bool TRACE, bool NT, bool WIDE>
 __device__ __forceinline__ void node_update(const AdrArgs<Real> &a, int x, int y)
 {
     const size_t id = (size_t)y * a.nxp + x;
@@ -203,9 +210,9 @@ __device__ __forceinline__ void node_update(const AdrArgs<Real> &a, int x, int y
     Acc h[S][5];
 #pragma unroll
     for (int s = 0; s < S; ++s)
-        pull5<Real, Acc, NT>(a.src + (size_t)s * 5 * P, P, id, x, a.nx, a.nxp, m, s == 0, inlet_e,
-                             h[s]);
-    collide_react_store<Real, Acc, S, TRACE, NT>(a, id, m, h);
+        pull5<Real, Acc, NT, WIDE>(a.src + (size_t)s * 5 * P, P, id, x, a.nx, a.nxp, m, s == 0,
+                                   inlet_e, h[s]);
+    collide_react_store<Real, Acc, S, TRACE, NT, WIDE>(a, id, m, h);
 }
 
 // Node update for the reaction variant (MODE 1) and/or the periodic box,
@@ -231,8 +238,8 @@ __device__ __forceinline__ void node_update_ext(const AdrArgs<Real> &a, int x, i
         const double inlet_e = 2.0 * w5<double>(DE) * (a.cin - a.cref);
 #pragma unroll
         for (int s = 0; s < S; ++s)
-            pull5<Real, double, NT>(a.src + (size_t)s * 5 * P, P, id, x, a.nx, a.nxp, m, s == 0,
-                                    inlet_e, h[s]);
+            pull5<Real, double, NT, true>(a.src + (size_t)s * 5 * P, P, id, x, a.nx, a.nxp, m,
+                                          s == 0, inlet_e, h[s]);
     }
     collide_react<Real, double, S, false, MODE>(a, id, m, double(a.ua[id]), double(a.ua[P + id]),
                                                 h, nb);

@@ -287,6 +287,7 @@ lbf_status lbf_create(const lbf_params *p, lbf_ctx *out)
     c->Lv.fp32_math = c->L.fp32_math = (p->flags & 16) != 0;
     c->Lv.mode = c->L.mode = p->reaction_mode;
     c->Lv.periodic = c->L.periodic = p->boundary == 1;
+    c->Lv.wide = c->L.wide = wide_lattice(c->plane, p->real_bytes, p->flags);
     c->flow_fp32_math = (p->flags & (16 | 32)) != 0;
     c->valid = true;
     return LBF_OK;

@@ -56,7 +56,7 @@ __device__ __forceinline__ void swap_parity(AdrArgs<Real> &a, int parity)
 // prefetched, the instance's argument block reused while the instance does
 // not change).  Otherwise one block per table slot; slots past the live
 // count exit at once.
-template <typename Real, int S, bool NT, bool PERSIST>
+template <typename Real, int S, bool NT, bool PERSIST, bool WIDE>
 __global__ __launch_bounds__(256) void k_batch_adr(const Inst<Real> *insts, const int4 *tiles,
                                                    const int *ntiles, int parity, int tx, int ty)
 {
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256) void k_batch_adr(const Inst<Real> *insts, cons
         AdrArgs<Real> a = insts[T.x].adr;
         swap_parity(a, parity);
         const int x = T.y * tx + lx, y = T.z * ty + ly;
-        if (x < a.nx && y < a.ny) adr::node_update<Real, double, S, false, NT>(a, x, y);
+        if (x < a.nx && y < a.ny) adr::node_update<Real, double, S, false, NT, WIDE>(a, x, y);
         return;
     }
     int t0, t1;
@@ -85,12 +85,12 @@ __global__ __launch_bounds__(256) void k_batch_adr(const Inst<Real> *insts, cons
             swap_parity(a, parity);
         }
         const int x = T.y * tx + lx, y = T.z * ty + ly;
-        if (x < a.nx && y < a.ny) adr::node_update<Real, double, S, false, NT>(a, x, y);
+        if (x < a.nx && y < a.ny) adr::node_update<Real, double, S, false, NT, WIDE>(a, x, y);
         T = Tn;
     }
 }
 
-template <typename Real, bool WRITE_U, bool NT>
+template <typename Real, bool WRITE_U, bool NT, bool WIDE>
 __global__ __launch_bounds__(256) void k_batch_flow(const Inst<Real> *insts, const int4 *tiles,
                                                     const int *ntiles, int parity, int tx, int ty)
 {
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(256) void k_batch_flow(const Inst<Real> *insts, con
         }
         const int x = T.y * tx + (int)threadIdx.x % tx;
         const int y = T.z * ty + (int)threadIdx.x / tx;
-        if (x < a.nx && y < a.ny) flow::node_update<Real, double, WRITE_U, NT>(a, x, y);
+        if (x < a.nx && y < a.ny) flow::node_update<Real, double, WRITE_U, NT, WIDE>(a, x, y);
     }
 }
 
@@ -214,6 +214,7 @@ struct lbf_batch_s {
     int tx = 256, ty = 1, grid = 2048;
     bool persistent = true;
     bool nontemporal = true;
+    bool wide = true;  // 64-bit population offsets in the node updates
     char *ws = nullptr;
     hipStream_t stream = nullptr, cap_stream = nullptr;
     std::string err;
@@ -291,7 +292,7 @@ hipError_t set_active(lbf_batch b, const std::vector<int> &act)
     return e;
 }
 
-template <typename Real, bool NT>
+template <typename Real, bool NT, bool WIDE>
 void batch_launch(lbf_batch b, int kind, int parity, bool write_u, hipStream_t s)
 {
     const int4 *tiles = (const int4 *)(b->ws + b->off_tiles);
@@ -302,32 +303,38 @@ void batch_launch(lbf_batch b, int kind, int parity, bool write_u, hipStream_t s
         const dim3 ga(b->persistent ? b->grid : b->max_tiles);
         if (b->p[0].nspecies == 2) {
             if (b->persistent)
-                hipLaunchKernelGGL((k_batch_adr<Real, 2, NT, true>), ga, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
+                hipLaunchKernelGGL((k_batch_adr<Real, 2, NT, true, WIDE>), ga, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
             else
-                hipLaunchKernelGGL((k_batch_adr<Real, 2, NT, false>), ga, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
+                hipLaunchKernelGGL((k_batch_adr<Real, 2, NT, false, WIDE>), ga, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
         } else {
             if (b->persistent)
-                hipLaunchKernelGGL((k_batch_adr<Real, 3, NT, true>), ga, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
+                hipLaunchKernelGGL((k_batch_adr<Real, 3, NT, true, WIDE>), ga, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
             else
-                hipLaunchKernelGGL((k_batch_adr<Real, 3, NT, false>), ga, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
+                hipLaunchKernelGGL((k_batch_adr<Real, 3, NT, false, WIDE>), ga, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
         }
     } else if (write_u) {
-        hipLaunchKernelGGL((k_batch_flow<Real, true, NT>), g, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
+        hipLaunchKernelGGL((k_batch_flow<Real, true, NT, WIDE>), g, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
     } else {
-        hipLaunchKernelGGL((k_batch_flow<Real, false, NT>), g, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
+        hipLaunchKernelGGL((k_batch_flow<Real, false, NT, WIDE>), g, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
     }
 }
 
 hipError_t enqueue_batch_step(lbf_batch b, int kind, int parity, bool write_u, hipStream_t s)
 {
-    const bool nt = b->nontemporal;
-    if (b->p[0].real_bytes == 4) {
-        if (nt) batch_launch<float, true>(b, kind, parity, write_u, s);
-        else batch_launch<float, false>(b, kind, parity, write_u, s);
-    } else {
-        if (nt) batch_launch<double, true>(b, kind, parity, write_u, s);
-        else batch_launch<double, false>(b, kind, parity, write_u, s);
-    }
+    const int sel = (b->nontemporal ? 1 : 0) | (b->wide ? 2 : 0);
+    auto launch = [&](auto real) {
+        using Real = decltype(real);
+        switch (sel) {
+        case 0: batch_launch<Real, false, false>(b, kind, parity, write_u, s); break;
+        case 1: batch_launch<Real, true, false>(b, kind, parity, write_u, s); break;
+        case 2: batch_launch<Real, false, true>(b, kind, parity, write_u, s); break;
+        default: batch_launch<Real, true, true>(b, kind, parity, write_u, s); break;
+        }
+    };
+    if (b->p[0].real_bytes == 4)
+        launch(float(0));
+    else
+        launch(double(0));
     return hipGetLastError();
 }
 
@@ -436,6 +443,9 @@ lbf_status lbf_batch_create(int n, const lbf_params *params, lbf_batch *out)
     for (int i = 0; i < n; ++i)
         adr_state += 2 * (size_t)p0.nspecies * 5 * p0.real_bytes * b->ctx[i].plane;
     b->nontemporal = (adr_state > NT_MIN_BYTES || (p0.flags & 64)) && !(p0.flags & 2);
+    b->wide = false;
+    for (int i = 0; i < n; ++i)
+        b->wide = b->wide || wide_lattice(b->ctx[i].plane, p0.real_bytes, params[i].flags);
     if (b->tx * b->ty > 256 || (b->tx * b->ty) % 64)
         return bfail(b, LBF_EINVAL, "batched tiles: tile_x * tile_y must be a multiple of 64, <= 256");
     size_t off = 0;

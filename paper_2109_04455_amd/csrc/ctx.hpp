@@ -60,6 +60,15 @@ constexpr long GRAPH_MIN_STEPS = 8;
 // step's working set.
 constexpr size_t NT_MIN_BYTES = (size_t)192 << 20;
 
+// Population blocks (the 9 flow planes, a species' 5 ADR planes, the 2
+// velocity planes) are addressed with 32-bit byte offsets while the largest,
+// the flow lattice, stays below 4 GiB; beyond that, or with flags bit 7, the
+// node updates use 64-bit offsets.
+inline bool wide_lattice(size_t plane, int real_bytes, int flags)
+{
+    return (flags & 128) || 9 * plane * (size_t)real_bytes > (size_t)UINT32_MAX;
+}
+
 lbf_status fail(Ctx *c, lbf_status s, const std::string &msg);
 lbf_status validate_params(const lbf_params *p, std::string &why);
 void layout(Ctx *c);

@@ -64,23 +64,29 @@ __device__ __forceinline__ void collide(Real (&h)[9], Real omega, Real &u, Real 
 }
 
 // Full update of node (x, y): gather (bounce-back, Zou-He), collide, store.
-template <typename Real, typename Acc, bool WRITE_U, bool NT>
+template <typename Real, typename Acc, bool WRITE_U, bool NT, bool WIDE>
 __device__ __forceinline__ void node_update(const FlowArgs<Real> &a, int x, int y)
 {
     const size_t id = (size_t)y * a.nxp + x;
     const unsigned m = a.mask9[id];
     if (m & MASK9_SOLID) return;
     const size_t P = a.plane;
+    using Off = off_t_<WIDE>;
+    constexpr Off B = sizeof(Real);
+    const Off PB = (Off)P * B, o = (Off)id * B;
+    const PopBlock<Real, NT, WIDE> in(a.src, 9 * PB);
     Acc h[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const int sx = x - CX[i];
         if (sx < 0 || sx >= a.nx) {
             h[i] = 0;  // open boundary: filled by Zou-He below
-        } else if (i != 0 && ((m >> (OPP[i] - 1)) & 1u)) {
-            h[i] = Acc(ld<NT>(a.src + OPP[i] * P + id));  // half-way bounce-back
         } else {
-            h[i] = Acc(ld<NT>(a.src + i * P + id - CX[i] - (ptrdiff_t)CY[i] * a.nxp));
+            // half-way bounce-back reads the node's own opposite population,
+            // else the population i of node id - c_i
+            const bool wall = i != 0 && ((m >> (OPP[i] - 1)) & 1u);
+            const Off back = (Off)(ptrdiff_t)(CX[i] + CY[i] * a.nxp) * B;  // modular
+            h[i] = Acc(in.load(wall ? o + OPP[i] * PB : o + i * PB - back));
         }
     }
     if (x == 0) {
@@ -108,8 +114,11 @@ __device__ __forceinline__ void node_update(const FlowArgs<Real> &a, int x, int 
         a.u[id] = Real(u);
         a.u[P + id] = Real(v);
     }
+    {
+        const PopBlock<Real, NT, WIDE> out(a.dst, 9 * PB);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) st<NT>(a.dst + i * P + id, Real(h[i]));
+        for (int i = 0; i < 9; ++i) out.store(o + i * PB, Real(h[i]));
+    }
 }
 
 }  // namespace flow

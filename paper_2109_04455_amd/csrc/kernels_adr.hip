@@ -132,13 +132,13 @@ __global__ __launch_bounds__(256) void k_adr_step_vec(AdrArgs<Real> a)
         for (int i = 0; i < 5; ++i) vstore<Real, V, NT>(a.dst + (s * 5 + i) * P + id0, out[s][i]);
 }
 
-template <typename Real, typename Acc, int S, bool TRACE, bool NT>
+template <typename Real, typename Acc, int S, bool TRACE, bool NT, bool WIDE>
 __global__ __launch_bounds__(1024) void k_adr_step(AdrArgs<Real> a)
 {
     int x, y;
     tile_coords(a.L, x, y);
     if (x >= a.nx || y >= a.ny) return;
-    adr::node_update<Real, Acc, S, TRACE, NT>(a, x, y);
+    adr::node_update<Real, Acc, S, TRACE, NT, WIDE>(a, x, y);
 }
 
 // Reaction variant and/or periodic box (FP64 arithmetic, no trace).
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(1024) void k_concentration(AdrArgs<Real> a, int spe
             pull5_periodic<Real, double, false>(a.src + (size_t)species * 5 * a.plane, a.plane, id,
                                                 nb, m, h);
         } else {
-            pull5<Real, double, false>(a.src + (size_t)species * 5 * a.plane, a.plane, id, x, a.nx,
+            pull5<Real, double, false, true>(a.src + (size_t)species * 5 * a.plane, a.plane, id, x, a.nx,
                                        a.nxp, m, species == 0, inlet_e, h);
         }
         c = (species == 0 ? a.cref : 0.0) + (h[0] + h[1] + h[2] + h[3] + h[4]);
@@ -238,11 +238,11 @@ __global__ __launch_bounds__(256) void k_trace_conc(AdrArgs<Real> a, const int32
     const unsigned m = a.mask5[id];
     const double inlet_e = 2.0 * w5<double>(DE) * (a.cin - a.cref);
     double h[5];
-    pull5<Real, double, false>(a.src, a.plane, id, x, a.nx, a.nxp, m, true, inlet_e, h);
+    pull5<Real, double, false, true>(a.src, a.plane, id, x, a.nx, a.nxp, m, true, inlet_e, h);
     a.trace[2 * t] = Real(a.cref + (h[0] + h[1] + h[2] + h[3] + h[4]));
     double cb = 0;
     if (S == 3) {
-        pull5<Real, double, false>(a.src + 5 * a.plane, a.plane, id, x, a.nx, a.nxp, m, false,
+        pull5<Real, double, false, true>(a.src + 5 * a.plane, a.plane, id, x, a.nx, a.nxp, m, false,
                                    inlet_e, h);
         cb = h[0] + h[1] + h[2] + h[3] + h[4];
     }
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(256) void k_totals(AdrArgs<Real> a, double *partial
             if (a.L.periodic)
                 pull5_periodic<Real, double, false>(a.src + (size_t)s * 5 * a.plane, a.plane, id, nb, m, h);
             else
-                pull5<Real, double, false>(a.src + (size_t)s * 5 * a.plane, a.plane, id, x, a.nx,
+                pull5<Real, double, false, true>(a.src + (size_t)s * 5 * a.plane, a.plane, id, x, a.nx,
                                            a.nxp, m, s == 0, inlet_e, h);
             acc[s] += (s == 0 ? a.cref : 0.0) + (h[0] + h[1] + h[2] + h[3] + h[4]);
         }
@@ -380,8 +380,12 @@ void step_launch(const AdrArgs<Real> &a, hipStream_t s)
     if (a.L.vec)
         hipLaunchKernelGGL((k_adr_step_vec<Real, Acc, S, TRACE, V, NT>), a.L.grid(), a.L.block(), 0,
                            s, a);
+    else if (a.L.wide)
+        hipLaunchKernelGGL((k_adr_step<Real, Acc, S, TRACE, NT, true>), a.L.grid(), a.L.block(), 0,
+                           s, a);
     else
-        hipLaunchKernelGGL((k_adr_step<Real, Acc, S, TRACE, NT>), a.L.grid(), a.L.block(), 0, s, a);
+        hipLaunchKernelGGL((k_adr_step<Real, Acc, S, TRACE, NT, false>), a.L.grid(), a.L.block(),
+                           0, s, a);
 }
 
 template <typename Real, typename Acc, int S>

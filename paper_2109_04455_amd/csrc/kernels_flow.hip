@@ -19,30 +19,39 @@ namespace {
 
 using namespace flow;
 
-template <typename Real, typename Acc, bool WRITE_U, bool NT>
+template <typename Real, typename Acc, bool WRITE_U, bool NT, bool WIDE>
 __global__ __launch_bounds__(1024) void k_flow_step(FlowArgs<Real> a)
 {
     int x, y;
     tile_coords(a.L, x, y);
     if (x >= a.nx || y >= a.ny) return;
-    flow::node_update<Real, Acc, WRITE_U, NT>(a, x, y);
+    flow::node_update<Real, Acc, WRITE_U, NT, WIDE>(a, x, y);
+}
+
+template <typename Real, typename Acc, bool WIDE>
+void flow_launch_w(bool write_u, const FlowArgs<Real> &a, hipStream_t s)
+{
+    const dim3 g = a.L.grid(), b = a.L.block();
+    if (a.L.nontemporal) {
+        if (write_u)
+            hipLaunchKernelGGL((k_flow_step<Real, Acc, true, true, WIDE>), g, b, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_flow_step<Real, Acc, false, true, WIDE>), g, b, 0, s, a);
+    } else {
+        if (write_u)
+            hipLaunchKernelGGL((k_flow_step<Real, Acc, true, false, WIDE>), g, b, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_flow_step<Real, Acc, false, false, WIDE>), g, b, 0, s, a);
+    }
 }
 
 template <typename Real, typename Acc>
 void flow_launch_acc(bool write_u, const FlowArgs<Real> &a, hipStream_t s)
 {
-    const dim3 g = a.L.grid(), b = a.L.block();
-    if (a.L.nontemporal) {
-        if (write_u)
-            hipLaunchKernelGGL((k_flow_step<Real, Acc, true, true>), g, b, 0, s, a);
-        else
-            hipLaunchKernelGGL((k_flow_step<Real, Acc, false, true>), g, b, 0, s, a);
-    } else {
-        if (write_u)
-            hipLaunchKernelGGL((k_flow_step<Real, Acc, true, false>), g, b, 0, s, a);
-        else
-            hipLaunchKernelGGL((k_flow_step<Real, Acc, false, false>), g, b, 0, s, a);
-    }
+    if (a.L.wide)
+        flow_launch_w<Real, Acc, true>(write_u, a, s);
+    else
+        flow_launch_w<Real, Acc, false>(write_u, a, s);
 }
 
 template <typename Real>

@@ -46,6 +46,7 @@ struct Launch {
     bool fp32_math = false;    // FP32 storage: compute in FP32 instead of FP64
     int mode = 0;              // ADR reaction: 0 links, 1 all populations next to catalysts
     bool periodic = false;     // ADR lattice periodic in x and y (no inlet / outlet)
+    bool wide = true;          // 64-bit population offsets (a 9-plane lattice >= 4 GiB)
     dim3 grid() const { return dim3(gx * gy, 1, 1); }
     dim3 block() const { return dim3(tx * ty, 1, 1); }
 };

@@ -3,6 +3,8 @@
 
 #include "lbf_internal.hpp"
 
+#include <type_traits>
+
 namespace lbf {
 
 // Map the hardware block to a tile.  Blocks of one launch are handed to the
@@ -44,6 +46,67 @@ __device__ __forceinline__ void st(Real *p, Real v)
     else
         *p = v;
 }
+
+// Reads and writes of a block of population planes at byte offsets from its
+// base.  Narrow blocks (< 4 GiB) go through a buffer descriptor (base and
+// byte range, wavefront-uniform, in scalar registers) with a 32-bit offset
+// per lane: a choice between two sources (bounce-back or neighbour) is then a
+// choice of offset and no lane does 64-bit address arithmetic; an offset
+// beyond the range reads 0 and drops a store instead of touching memory.
+// Word 3 0x00020000 is the raw 32-bit format of a GFX9 descriptor; cache-
+// policy bit 1 is the non-temporal hint.  WIDE blocks use a plain pointer
+// and 64-bit offsets.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+
+template <bool WIDE>
+using off_t_ = typename std::conditional<WIDE, size_t, uint32_t>::type;
+
+template <typename Real, bool NT, bool WIDE>
+struct PopBlock;
+
+template <typename Real, bool NT>
+struct PopBlock<Real, NT, false> {
+    rsrc_t r;
+    __device__ __forceinline__ PopBlock(const Real *base, uint32_t bytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<Real *>(base), 0, (int)bytes, 0x00020000))
+    {
+    }
+    __device__ __forceinline__ Real load(uint32_t off) const
+    {
+        constexpr int aux = NT ? 2 : 0;
+        if constexpr (sizeof(Real) == 4)
+            return __builtin_bit_cast(Real, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, aux));
+        else
+            return __builtin_bit_cast(Real, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, aux));
+    }
+    __device__ __forceinline__ void store(uint32_t off, Real v) const
+    {
+        constexpr int aux = NT ? 2 : 0;
+        if constexpr (sizeof(Real) == 4)
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, aux);
+        else
+            __builtin_amdgcn_raw_buffer_store_b64(
+                __builtin_bit_cast(unsigned int __attribute__((ext_vector_type(2))), v), r, off, 0,
+                aux);
+    }
+};
+
+template <typename Real, bool NT>
+struct PopBlock<Real, NT, true> {
+    const char *p;
+    __device__ __forceinline__ PopBlock(const Real *base, size_t)
+        : p(reinterpret_cast<const char *>(base))
+    {
+    }
+    __device__ __forceinline__ Real load(size_t off) const
+    {
+        return ld<NT>(reinterpret_cast<const Real *>(p + off));
+    }
+    __device__ __forceinline__ void store(size_t off, Real v) const
+    {
+        st<NT>(reinterpret_cast<Real *>(const_cast<char *>(p) + off), v);
+    }
+};
 
 inline Launch make_launch(int nx, int ny, int tx, int ty)
 {

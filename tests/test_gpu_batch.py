@@ -36,11 +36,13 @@ def _instances(n=6, ny=48, seed=5):
     return ws
 
 
-@pytest.mark.parametrize("real", ["f32", "f64"])
-def test_batch_equals_single_instance_path(real):
+@pytest.mark.parametrize("real,flags", [("f32", 0), ("f64", 0), ("f32", 128)])
+def test_batch_equals_single_instance_path(real, flags):
+    # flags bit 7: the batch addresses populations with 64-bit offsets, the
+    # single-instance path with 32-bit ones; the arithmetic is the same
     import paper_2109_04455_amd as L
     ws = _instances()
-    b = L.Batch([_params(w, real) for w in ws])
+    b = L.Batch([_params(w, real, flags=flags) for w in ws])
     b.set_geometry([w.node_type for w in ws], [w.k for w in ws])
     b.flow(600, check_every=600, tol=0)
     eps, prod, steps = b.run(1500, check_every=500, tol=0)

@@ -252,3 +252,22 @@ def test_streaming_and_cached_accesses_agree(flags):
         c.adr_run(300, tol=0)
         out.append(c.concentration(1))
     assert torch.equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("real", ["f32", "f64"])
+def test_32bit_and_64bit_population_offsets_agree(real):
+    # flags bit 7 forces the 64-bit offsets that lattices of 4 GiB and more
+    # use; the addressing changes no arithmetic, so every field is bit-equal
+    w = make_workload("C1q")
+    out = []
+    for f in (0, 128):
+        c = _ctx(w, real, flags=f, variant=1)
+        c.flow_init()
+        c.flow_run(200)
+        ux, uy = c.get_velocity()
+        c.adr_init()
+        c.adr_run(300, tol=0)
+        out.append([ux, uy] + [c.concentration(s) for s in range(w.nspecies)])
+        c.close()
+    for a, b in zip(*out):
+        assert torch.equal(a, b)
