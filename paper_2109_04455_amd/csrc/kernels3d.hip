@@ -121,44 +121,51 @@ __device__ __forceinline__ void collide19(T (&h)[19], T omega, T fx, T (&u)[3])
     }
 }
 
+// Populations are read and written at 64-bit byte offsets from the lattice
+// base (32-bit buffer offsets, which pay off in 2D, measured slower here).
 template <typename Real, typename Acc, bool WRITE_U, bool NT>
 __global__ __launch_bounds__(1024) void k_flow_step3(FlowArgs3<Real> a)
 {
+    using Off = size_t;
+    constexpr Off QB = SEG * sizeof(Real);  // bytes between populations q and q + 1
     int x, row;
     tile_coords(a.L, x, row);
     const Geo &g = a.g;
     if (x >= g.nx || row >= g.ny * g.nz) return;
-    const size_t id = (size_t)row * g.nxp + x;
+    const Off id = (Off)row * (Off)g.nxp + (Off)x;
     const uint32_t m = a.mask19[id];
     if (m & MASK19_SOLID) return;
     const int y = row % g.ny, z = row / g.ny;
-    const size_t P = g.plane;
+    const Off PB = (Off)g.plane * sizeof(Real);
+    const PopBlock<Real, NT, true> in(a.src, 19 * PB), out(a.dst, 19 * PB);
+    const Off own = seg_off<19, Real>(id);
     Acc h[19];
-    h[0] = Acc(ld<NT>(a.src + pidx<19>(id, 0)));
+    h[0] = Acc(in.load(own));
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
         const int o = opp19(i);
+        Off src;
         if ((m >> (o - 1)) & 1u) {
-            h[i] = Acc(ld<NT>(a.src + pidx<19>(id, o)));  // half-way bounce-back
+            src = own + (Off)o * QB;  // half-way bounce-back
         } else {
             int sx = x - CX[i];
             sx = sx < 0 ? sx + g.nx : (sx >= g.nx ? sx - g.nx : sx);
-            const size_t sid = (size_t)row_of(g, y, z, -CY[i], -CZ[i]) * g.nxp + sx;
-            h[i] = Acc(ld<NT>(a.src + pidx<19>(sid, i)));
+            const Off sid = (Off)row_of(g, y, z, -CY[i], -CZ[i]) * (Off)g.nxp + (Off)sx;
+            src = seg_off<19, Real>(sid) + (Off)i * QB;
         }
+        h[i] = Acc(in.load(src));
     }
     Acc u[3];
     collide19(h, Acc(a.omega), Acc(a.fx), u);
     if (WRITE_U) {
         a.u[id] = Real(u[0]);
-        a.u[P + id] = Real(u[1]);
-        a.u[2 * P + id] = Real(u[2]);
+        a.u[g.plane + id] = Real(u[1]);
+        a.u[2 * g.plane + id] = Real(u[2]);
     }
 #pragma unroll
-    for (int i = 0; i < 19; ++i) st<NT>(a.dst + pidx<19>(id, i), Real(h[i]));
+    for (int i = 0; i < 19; ++i) out.store(own + (Off)i * QB, Real(h[i]));
 }
 
-// Rest fluid (h = 0) and its first collision; solids hold zeros.
 template <typename Real>
 __global__ __launch_bounds__(1024) void k_flow_init3(FlowArgs3<Real> a)
 {
@@ -283,58 +290,68 @@ __global__ void k_pad3(const Real *src, Real *dst, const uint8_t *type_pad, Geo 
 
 // ------------------------------------------------------------------- ADR ----
 // Gather the pre-collision shifted populations of one species (populations
-// q0 .. q0+6 of a lattice of NQ populations) at node id = (x, row) from the
-// previous post-collision lattice.  Directions 1..6 = +x, -x, +y, -y, +z, -z.
-template <typename Real, typename Acc, bool NT, int NQ>
-__device__ __forceinline__ void pull7(const Real *__restrict__ lat, int q0, size_t id, int x,
-                                      int nx, const size_t (&nb)[7], unsigned m, bool species_a,
-                                      Acc inlet_e, Acc (&h)[7])
+// q0 .. q0+6 of a lattice of NQ populations) at node (x, row) from the
+// previous post-collision lattice.  Directions 1..6 = +x, -x, +y, -y, +z, -z;
+// so[d]: byte offset (seg_off) of neighbour x + c_d, so[0] of the node itself.
+template <typename Real, typename Acc, int NQ, typename Blk, typename Off>
+__device__ __forceinline__ void pull7(const Blk &lat, int q0, const Off (&so)[7], int x, int nx,
+                                      unsigned m, bool species_a, Acc inlet_e, Acc (&h)[7])
 {
-    auto at = [&](size_t node, int d) { return Acc(ld<NT>(lat + pidx<NQ>(node, q0 + d))); };
-    h[0] = at(id, 0);
+    constexpr Off QB = SEG * sizeof(Real);
+    auto at = [&](int node, int d) { return Acc(lat.load(so[node] + (Off)(q0 + d) * QB)); };
+    h[0] = at(0, 0);
     // +x arrives from x - 1
     if (x == 0)
-        h[1] = species_a ? inlet_e - at(id, 2) : at(id, 2);
+        h[1] = species_a ? inlet_e - at(0, 2) : at(0, 2);
     else if (m & 2u)
-        h[1] = at(id, 2);
+        h[1] = at(0, 2);
     else
-        h[1] = at(nb[2], 1);
+        h[1] = at(2, 1);
     // -x arrives from x + 1
     if (x == nx - 1) {
         Acc sum = Acc(0);
 #pragma unroll
-        for (int j = 0; j < 7; ++j) sum += at(id, j);
-        h[2] = Acc(2) * w7<Acc>(2) * sum - at(id, 1);
+        for (int j = 0; j < 7; ++j) sum += at(0, j);
+        h[2] = Acc(2) * w7<Acc>(2) * sum - at(0, 1);
     } else if (m & 1u) {
-        h[2] = at(id, 1);
+        h[2] = at(0, 1);
     } else {
-        h[2] = at(nb[1], 2);
+        h[2] = at(1, 2);
     }
     // +-y, +-z: periodic; bounce-back at solid neighbours
 #pragma unroll
     for (int d = 3; d < 7; ++d) {
         const int o = d & 1 ? d + 1 : d - 1;
-        h[d] = (m >> (o - 1)) & 1u ? at(id, o) : at(nb[o], d);
+        h[d] = (m >> (o - 1)) & 1u ? at(0, o) : at(o, d);
     }
 }
 
 // Indices of the six neighbours x + c_d (x unwrapped: only used in range).
-__device__ __forceinline__ void neighbours7(const Geo &g, int x, int y, int z, size_t (&nb)[7])
+template <typename Idx>
+__device__ __forceinline__ void neighbours7(const Geo &g, int x, int y, int z, Idx (&nb)[7])
 {
-    const size_t r = (size_t)(z * g.ny + y) * g.nxp;
+    const Idx r = (Idx)(z * g.ny + y) * (Idx)g.nxp;
     nb[0] = r + x;
     nb[1] = r + x + 1;
     nb[2] = r + x - 1;
-    nb[3] = (size_t)row_of(g, y, z, 1, 0) * g.nxp + x;
-    nb[4] = (size_t)row_of(g, y, z, -1, 0) * g.nxp + x;
-    nb[5] = (size_t)row_of(g, y, z, 0, 1) * g.nxp + x;
-    nb[6] = (size_t)row_of(g, y, z, 0, -1) * g.nxp + x;
+    nb[3] = (Idx)row_of(g, y, z, 1, 0) * (Idx)g.nxp + x;
+    nb[4] = (Idx)row_of(g, y, z, -1, 0) * (Idx)g.nxp + x;
+    nb[5] = (Idx)row_of(g, y, z, 0, 1) * (Idx)g.nxp + x;
+    nb[6] = (Idx)row_of(g, y, z, 0, -1) * (Idx)g.nxp + x;
+}
+
+// Byte offsets (seg_off) of a node's neighbours in a lattice of NQ populations.
+template <int NQ, typename Real, typename Idx>
+__device__ __forceinline__ void neighbour_offsets(const Idx (&nb)[7], Idx (&so)[7])
+{
+#pragma unroll
+    for (int d = 0; d < 7; ++d) so[d] = seg_off<NQ, Real>(nb[d]);
 }
 
 // Collide (second-order equilibrium, cs^2 = 1/4) and react one node in place.
-template <typename Real, typename Acc, int S>
+template <typename Real, typename Acc, int S, typename Idx>
 __device__ __forceinline__ void collide_react7(const AdrArgs3<Real> &a, unsigned m,
-                                               const size_t (&nb)[7], Acc u, Acc v, Acc w,
+                                               const Idx (&nb)[7], Acc u, Acc v, Acc w,
                                                Acc (&h)[S][7])
 {
     const Acc uu = Acc(2) * (u * u + v * v + w * w);
@@ -368,7 +385,7 @@ __device__ __forceinline__ void collide_react7(const AdrArgs3<Real> &a, unsigned
 #pragma unroll
         for (int d = 1; d < 7; ++d) {
             if (!((m >> (d + 5)) & 1u)) continue;
-            const size_t sid = nb[d];
+            const Idx sid = nb[d];
             const Acc k = Acc(a.kr[sid]);
             if (a.type[sid] == 2) {
                 const Acc r = k * w7<Acc>(d) * c[0];
@@ -386,27 +403,34 @@ __device__ __forceinline__ void collide_react7(const AdrArgs3<Real> &a, unsigned
 template <typename Real, typename Acc, int S, bool NT>
 __global__ __launch_bounds__(1024) void k_adr_step3(AdrArgs3<Real> a)
 {
+    using Off = size_t;
+    constexpr int NQ = 7 * S;
+    constexpr Off QB = SEG * sizeof(Real);
     int x, row;
     tile_coords(a.L, x, row);
     const Geo &g = a.g;
     if (x >= g.nx || row >= g.ny * g.nz) return;
-    const size_t id = (size_t)row * g.nxp + x;
+    const Off id = (Off)row * (Off)g.nxp + (Off)x;
     const unsigned m = a.mask7[id];
     if (m == MASK7_SOLID) return;
     const int y = row % g.ny, z = row / g.ny;
-    const size_t P = g.plane;
-    size_t nb[7];
+    const Off PB = (Off)g.plane * sizeof(Real);
+    Off nb[7], so[7];
     neighbours7(g, x, y, z, nb);
+    neighbour_offsets<NQ, Real>(nb, so);
+    const PopBlock<Real, NT, true> in(a.src, NQ * PB), out(a.dst, NQ * PB);
+    const PopBlock<Real, false, true> vel(a.ua, 3 * PB);
     const Acc inlet_e = Acc(2) * w7<Acc>(1) * (Acc(a.cin) - Acc(a.cref));
     Acc h[S][7];
 #pragma unroll
-    for (int s = 0; s < S; ++s)
-        pull7<Real, Acc, NT, 7 * S>(a.src, 7 * s, id, x, g.nx, nb, m, s == 0, inlet_e, h[s]);
-    collide_react7<Real, Acc, S>(a, m, nb, Acc(a.ua[id]), Acc(a.ua[P + id]), Acc(a.ua[2 * P + id]), h);
+    for (int s = 0; s < S; ++s) pull7<Real, Acc, NQ>(in, 7 * s, so, x, g.nx, m, s == 0, inlet_e, h[s]);
+    const Off ob = id * (Off)sizeof(Real);
+    collide_react7<Real, Acc, S>(a, m, nb, Acc(vel.load(ob)), Acc(vel.load(ob + PB)),
+                                 Acc(vel.load(ob + 2 * PB)), h);
 #pragma unroll
     for (int s = 0; s < S; ++s)
 #pragma unroll
-        for (int i = 0; i < 7; ++i) st<NT>(a.dst + pidx<7 * S>(id, 7 * s + i), Real(h[s][i]));
+        for (int i = 0; i < 7; ++i) out.store(so[0] + (Off)(7 * s + i) * QB, Real(h[s][i]));
 }
 
 // A at equilibrium with C = c_in, B = C = 0, then the first collision.
@@ -488,12 +512,13 @@ __global__ __launch_bounds__(1024) void k_conc3(AdrArgs3<Real> a, int species, R
     double c = 0.0;
     if (m != MASK7_SOLID) {
         const int y = row % g.ny, z = row / g.ny;
-        size_t nb[7];
+        size_t nb[7], so[7];
         neighbours7(g, x, y, z, nb);
+        neighbour_offsets<7 * S, Real>(nb, so);
+        const PopBlock<Real, false, true> lat(a.src, 0);
         double h[7];
         const double inlet_e = 2.0 * 0.125 * (a.cin - a.cref);
-        pull7<Real, double, false, 7 * S>(a.src, 7 * species, id, x, g.nx, nb, m, species == 0,
-                                          inlet_e, h);
+        pull7<Real, double, 7 * S>(lat, 7 * species, so, x, g.nx, m, species == 0, inlet_e, h);
         c = species == 0 ? a.cref : 0.0;
         for (int i = 0; i < 7; ++i) c += h[i];
     }
@@ -516,11 +541,13 @@ __global__ __launch_bounds__(256) void k_totals3(AdrArgs3<Real> a, double *parti
         const unsigned m = a.mask7[id];
         if (m == MASK7_SOLID) continue;
         const int y = row % g.ny, z = row / g.ny;
-        size_t nb[7];
+        size_t nb[7], so[7];
         neighbours7(g, x, y, z, nb);
+        neighbour_offsets<7 * S, Real>(nb, so);
+        const PopBlock<Real, false, true> lat(a.src, 0);
         for (int s = 0; s < S; ++s) {
             double h[7];
-            pull7<Real, double, false, 7 * S>(a.src, 7 * s, id, x, g.nx, nb, m, s == 0, inlet_e, h);
+            pull7<Real, double, 7 * S>(lat, 7 * s, so, x, g.nx, m, s == 0, inlet_e, h);
             double c = s == 0 ? a.cref : 0.0;
             for (int j = 0; j < 7; ++j) c += h[j];
             acc[s] += c;

@@ -73,6 +73,15 @@ __device__ __forceinline__ size_t pidx(size_t node, int q)
     return ((node / SEG) * NQ + (size_t)q) * SEG + node % SEG;
 }
 
+// Byte offset of population 0 of `node` in a lattice of NQ populations of
+// type Real (the layout of pidx); population q lies q * SEG * sizeof(Real)
+// bytes further.
+template <int NQ, typename Real, typename Off>
+__device__ __forceinline__ Off seg_off(Off node)
+{
+    return ((node / SEG) * (Off)(NQ * SEG) + node % SEG) * (Off)sizeof(Real);
+}
+
 // Row index of (y + dy, z + dz), periodic in y and z (|dy|, |dz| <= 1).
 __device__ __forceinline__ int row_of(const Geo &g, int y, int z, int dy, int dz)
 {
