@@ -26,18 +26,16 @@ __device__ __forceinline__ T w5(int i)
 }
 
 // Gather the pre-collision (shifted) populations of one species at node
-// (x, y) from the post-collision lattice `src` (base of this species; plane d
-// starts at src + d P).  Offsets are in bytes from src, so a choice between
-// two sources is a choice of offset (see PopBlock).
-template <typename Real, typename Acc, bool NT, bool WIDE>
-__device__ __forceinline__ void pull5(const Real *__restrict__ src, size_t P, size_t id, int x,
-                                      int nx, int nxp, unsigned m, bool species_a, Acc inlet_e,
-                                      Acc (&h)[5])
+// (x, y) from a block of its 5 post-collision planes: plane d starts d PB
+// bytes after the block base, rows are RB bytes apart and the node itself is
+// at byte offset o.  A choice between two sources (bounce-back or
+// neighbour) is a choice of offset.  Blk: PopBlock (lattice in HBM) or
+// LdsBlock (a tile in LDS).
+template <typename Acc, typename Blk, typename Off>
+__device__ __forceinline__ void pull5_at(const Blk &blk, Off PB, Off RB, Off o, int x, int nx,
+                                         unsigned m, bool species_a, Acc inlet_e, Acc (&h)[5])
 {
-    using Off = off_t_<WIDE>;
-    constexpr Off B = sizeof(Real);
-    const Off PB = (Off)P * B, o = (Off)id * B, RB = (Off)nxp * B;
-    const PopBlock<Real, NT, WIDE> blk(src, 5 * PB);
+    constexpr Off B = sizeof(typename Blk::real_type);
     auto at = [&](Off off) { return Acc(blk.load(off)); };
     const Off oE = o + DE * PB, oN = o + DN * PB, oW = o + DW * PB, oS = o + DS * PB;
     h[0] = at(o);
@@ -57,6 +55,20 @@ __device__ __forceinline__ void pull5(const Real *__restrict__ src, size_t P, si
     }
     // S arrives from y + 1
     h[DS] = at((m & BIT_N) ? oN : oS + RB);
+}
+
+// The same from the lattice in HBM: `src` is the base of this species, P the
+// plane size in nodes, id the node index.
+template <typename Real, typename Acc, bool NT, bool WIDE>
+__device__ __forceinline__ void pull5(const Real *__restrict__ src, size_t P, size_t id, int x,
+                                      int nx, int nxp, unsigned m, bool species_a, Acc inlet_e,
+                                      Acc (&h)[5])
+{
+    using Off = off_t_<WIDE>;
+    constexpr Off B = sizeof(Real);
+    const Off PB = (Off)P * B;
+    const PopBlock<Real, NT, WIDE> blk(src, 5 * PB);
+    pull5_at<Acc>(blk, PB, (Off)nxp * B, (Off)id * B, x, nx, m, species_a, inlet_e, h);
 }
 
 // Gather for a box periodic in x and y (no inlet or outlet); solid

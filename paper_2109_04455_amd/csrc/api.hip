@@ -106,6 +106,32 @@ hipError_t enqueue_adr_step(Ctx *c, int src_buf, hipStream_t s, void *trace_slot
     return launch_adr_step(c->p.real_bytes, c->p.nspecies, trace_slot != nullptr, af, ad, s);
 }
 
+// Enqueue two ADR steps from lattice `src_buf`; the result lands in the
+// other lattice, as after one step (the intermediate state stays in LDS).
+hipError_t enqueue_adr_pair(Ctx *c, int src_buf, hipStream_t s)
+{
+    AdrArgs<float> af = adr_args<float>(c, src_buf);
+    AdrArgs<double> ad = adr_args<double>(c, src_buf);
+    af.L = ad.L = c->Lp;
+    return launch_adr_pair(c->p.real_bytes, c->p.nspecies, af, ad, s);
+}
+
+// An ADR block of n steps runs as `pairs` two-step launches followed by
+// n - 2 pairs single steps; the last step is always a single one, so that
+// the other lattice holds the state one step back (the outlet fluxes read
+// it).  Returns the number of lattice swaps.
+long adr_pairs(const Ctx *c, long n) { return c->pair && n >= 3 ? (n - 1) / 2 : 0; }
+
+hipError_t enqueue_adr_block(Ctx *c, int &par, long n, hipStream_t s)
+{
+    const long pairs = adr_pairs(c, n);
+    hipError_t e = hipSuccess;
+    for (long i = 0; i < pairs && e == hipSuccess; ++i, par ^= 1) e = enqueue_adr_pair(c, par, s);
+    for (long i = 2 * pairs; i < n && e == hipSuccess; ++i, par ^= 1)
+        e = enqueue_adr_step(c, par, s, nullptr);
+    return e;
+}
+
 hipError_t enqueue_flow_step(Ctx *c, int src_buf, bool write_u, hipStream_t s)
 {
     return launch_flow_step(c->p.real_bytes, write_u, flow_args<float>(c, src_buf),
@@ -118,9 +144,13 @@ lbf_status run_steps(Ctx *c, int kind, long n)
     if (n <= 0) return LBF_OK;
     int &par = kind == KIND_ADR ? c->gpar : c->fpar;
     if (n < GRAPH_MIN_STEPS) {
+        if (kind == KIND_ADR) {
+            hipError_t e = enqueue_adr_block(c, par, n, c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "step launch");
+            return LBF_OK;
+        }
         for (long i = 0; i < n; ++i) {
-            hipError_t e = kind == KIND_ADR ? enqueue_adr_step(c, par, c->stream, nullptr)
-                                            : enqueue_flow_step(c, par, i == n - 1, c->stream);
+            hipError_t e = enqueue_flow_step(c, par, i == n - 1, c->stream);
             if (e != hipSuccess) return hip_fail(c, e, "step launch");
             par ^= 1;
         }
@@ -133,10 +163,11 @@ lbf_status run_steps(Ctx *c, int kind, long n)
         if (e != hipSuccess) return hip_fail(c, e, "hipStreamBeginCapture");
         int p = par;
         hipError_t le = hipSuccess;
-        for (long i = 0; i < n && le == hipSuccess; ++i) {
-            le = kind == KIND_ADR ? enqueue_adr_step(c, p, c->cap_stream, nullptr)
-                                  : enqueue_flow_step(c, p, i == n - 1, c->cap_stream);
-            p ^= 1;
+        if (kind == KIND_ADR) {
+            le = enqueue_adr_block(c, p, n, c->cap_stream);
+        } else {
+            for (long i = 0; i < n && le == hipSuccess; ++i, p ^= 1)
+                le = enqueue_flow_step(c, p, i == n - 1, c->cap_stream);
         }
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(c->cap_stream, &g);
@@ -153,7 +184,8 @@ lbf_status run_steps(Ctx *c, int kind, long n)
     }
     hipError_t e = hipGraphLaunch(it->second, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
-    if (n & 1) par ^= 1;
+    const long swaps = kind == KIND_ADR ? n - adr_pairs(c, n) : n;
+    if (swaps & 1) par ^= 1;
     return LBF_OK;
 }
 
@@ -288,6 +320,20 @@ lbf_status lbf_create(const lbf_params *p, lbf_ctx *out)
     c->Lv.mode = c->L.mode = p->reaction_mode;
     c->Lv.periodic = c->L.periodic = p->boundary == 1;
     c->Lv.wide = c->L.wide = wide_lattice(c->plane, p->real_bytes, p->flags);
+    // untraced steps of the link-reaction channel run two per launch unless
+    // flags bit 8 asks for one step per launch
+    c->pair = !ext && !(p->flags & 256);
+    if (c->pair) {
+        int tx, ty;
+        pair_tile(p->real_bytes, tx, ty);
+        c->Lp = c->L;
+        const Launch t = make_launch(p->nx, p->ny, tx, ty);
+        c->Lp.tx = t.tx;
+        c->Lp.ty = t.ty;
+        c->Lp.gx = t.gx;
+        c->Lp.gy = t.gy;
+        c->Lp.vec = false;
+    }
     c->flow_fp32_math = (p->flags & (16 | 32)) != 0;
     c->valid = true;
     return LBF_OK;

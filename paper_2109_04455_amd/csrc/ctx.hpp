@@ -19,6 +19,8 @@ struct lbf_ctx_s {
     double cref = 0;   // storage shift of species A
     lbf::Launch L;   // one node per thread
     lbf::Launch Lv;  // ADR step launch (vectorised or not, per params.variant)
+    lbf::Launch Lp;  // two-step ADR launch (when `pair`)
+    bool pair = false;  // untraced ADR steps run two per launch
     bool flow_fp32_math = false;  // flow step computes in FP32 (FP32 storage)
 
     // workspace (caller-owned) and its layout
@@ -78,6 +80,7 @@ lbf_status run_steps(Ctx *c, int kind, long n);
 lbf_status compute_fluxes(Ctx *c, double *out4);
 double efficiency_of(const double *N, int ns);
 hipError_t enqueue_adr_step(Ctx *c, int src_buf, hipStream_t s, void *trace_slot);
+hipError_t enqueue_adr_pair(Ctx *c, int src_buf, hipStream_t s);
 void adjoint_release(Ctx *c);
 
 // Kernel argument blocks for the context's own lattices.

@@ -141,6 +141,81 @@ __global__ __launch_bounds__(1024) void k_adr_step(AdrArgs<Real> a)
     adr::node_update<Real, Acc, S, TRACE, NT, WIDE>(a, x, y);
 }
 
+// Two steps per launch (temporal blocking).  A block owns 64 x (EY - 2)
+// output nodes (rows aligned to 64 nodes) and the extended tile of 66 x EY
+// nodes around them (a ring of one node).  Step 1 updates the extended tile
+// from the lattice in HBM and keeps the result in LDS, rounded to Real
+// exactly as a store to HBM would round it: wavefront w < EY takes the 64
+// core nodes of extended row w, wavefront EY the two ring columns of every
+// row.  Step 2 gathers the output nodes from LDS, one row per wavefront, and
+// writes them.  A ring node is computed by every block whose tile it borders;
+// its source reads mostly hit the L2 that the XCD-aware block order shares
+// between neighbouring tiles.  The lattice crosses HBM once per two steps.
+// NTL: streaming hint on the step-1 loads; NT: on the final stores.
+template <typename Real, typename Acc, int S, bool NTL, bool NT, bool WIDE, int EY>
+__global__ __launch_bounds__(64 * (EY + 1)) void k_adr_step2(AdrArgs<Real> a)
+{
+    constexpr int EX = 66, TY = EY - 2, EP = EX * EY;
+    __shared__ Real lds[5 * S * EP];
+    using Off = off_t_<WIDE>;
+    constexpr Off B = sizeof(Real);
+    int bx, by;
+    tile_of_block(a.L, bx, by);
+    const int x0 = bx * 64, y0 = by * TY;  // first output node
+    const int w = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
+    const size_t P = a.plane;
+    const Acc inlet_e = Acc(2) * w5<Acc>(DE) * (Acc(a.cin) - Acc(a.cref));
+    {
+        int ex, ey;
+        if (w < EY) {
+            ey = w;
+            ex = lane + 1;
+        } else {
+            ey = lane >> 1;
+            ex = (lane & 1) ? EX - 1 : 0;
+        }
+        const int x = x0 - 1 + ex, y = y0 - 1 + ey;
+        const bool inside = ey < EY && x >= 0 && x < a.nx && y >= 0 && y < a.ny;
+        const size_t id = (size_t)y * a.nxp + x;
+        const unsigned m = inside ? a.mask5[id] : MASK5_SOLID;
+        if (m != MASK5_SOLID) {
+            Acc h[S][5];
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                adr::pull5<Real, Acc, NTL, WIDE>(a.src + (size_t)s * 5 * P, P, id, x, a.nx, a.nxp,
+                                                 m, s == 0, inlet_e, h[s]);
+            const Off PB = (Off)P * B, o = (Off)id * B;
+            const PopBlock<Real, false, WIDE> vel(a.ua, 2 * PB);
+            adr::collide_react<Real, Acc, S, false>(a, id, m, Acc(vel.load(o)),
+                                                    Acc(vel.load(o + PB)), h);
+            const int e = ey * EX + ex;
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+#pragma unroll
+                for (int i = 0; i < 5; ++i) lds[(s * 5 + i) * EP + e] = Real(h[s][i]);
+        }
+    }
+    __syncthreads();
+    // Step 2 on the output rows.  The ring nodes a gather can reach (x - 1
+    // for x > 0, x + 1 for x < nx - 1, y +- 1 of a fluid node) were all
+    // updated above; ring nodes outside the lattice are never read (inlet and
+    // outlet rules, solid channel walls).
+    if (w >= TY) return;
+    const int x = x0 + lane, y = y0 + w;
+    if (x >= a.nx || y >= a.ny) return;
+    const size_t id = (size_t)y * a.nxp + x;
+    const unsigned m = a.mask5[id];
+    if (m == MASK5_SOLID) return;
+    constexpr uint32_t LB = sizeof(Real);
+    const uint32_t e = (uint32_t)((w + 1) * EX + lane + 1) * LB;
+    Acc h[S][5];
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+        adr::pull5_at<Acc>(LdsBlock<Real>{lds + s * 5 * EP}, (uint32_t)(EP * LB),
+                           (uint32_t)(EX * LB), e, x, a.nx, m, s == 0, inlet_e, h[s]);
+    adr::collide_react_store<Real, Acc, S, false, NT, WIDE>(a, id, m, h);
+}
+
 // Reaction variant and/or periodic box (FP64 arithmetic, no trace).
 template <typename Real, int S, bool NT, int MODE, bool PERIODIC>
 __global__ __launch_bounds__(1024) void k_adr_step_ext(AdrArgs<Real> a)
@@ -439,7 +514,57 @@ hipError_t step_dispatch(int ns, bool trace, const AdrArgs<Real> &a, hipStream_t
     return hipGetLastError();
 }
 
+// Extended tile of the two-step kernel: 66 x EY nodes around 64 x (EY - 2)
+// output nodes.  EY = 15 for FP32 storage (16 wavefronts and 58 KB of LDS per
+// block, two blocks per CU); 10 for FP64 (11 wavefronts, 77 KB).  Measured on
+// a 4096 x 1024 channel against EY = 6 .. 12 (FP32) and 4 .. 8 (FP64).
+template <typename Real>
+struct PairTile {
+    static constexpr int EY = sizeof(Real) == 4 ? 15 : 10;
+    static constexpr int TX = 64, TY = EY - 2;  // output nodes per block
+};
+
+template <typename Real, typename Acc, int S>
+void pair_launch(const AdrArgs<Real> &a, hipStream_t s)
+{
+    constexpr int EY = PairTile<Real>::EY;
+    const dim3 g = a.L.grid(), b(64 * (EY + 1));
+    const int sel = (a.L.nontemporal ? 1 : 0) | (a.L.wide ? 2 : 0);
+    switch (sel) {
+    case 0: hipLaunchKernelGGL((k_adr_step2<Real, Acc, S, false, false, false, EY>), g, b, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_adr_step2<Real, Acc, S, false, true, false, EY>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_adr_step2<Real, Acc, S, false, false, true, EY>), g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_adr_step2<Real, Acc, S, false, true, true, EY>), g, b, 0, s, a); break;
+    }
+}
+
+template <typename Real>
+hipError_t pair_dispatch(int ns, const AdrArgs<Real> &a, hipStream_t s)
+{
+    if (a.L.tx != PairTile<Real>::TX || a.L.ty != PairTile<Real>::TY) return hipErrorInvalidValue;
+    if constexpr (sizeof(Real) == 4) {
+        if (a.L.fp32_math) {
+            ns == 2 ? pair_launch<Real, float, 2>(a, s) : pair_launch<Real, float, 3>(a, s);
+            return hipGetLastError();
+        }
+    }
+    ns == 2 ? pair_launch<Real, double, 2>(a, s) : pair_launch<Real, double, 3>(a, s);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+void pair_tile(int real_bytes, int &tx, int &ty)
+{
+    tx = real_bytes == 4 ? PairTile<float>::TX : PairTile<double>::TX;
+    ty = real_bytes == 4 ? PairTile<float>::TY : PairTile<double>::TY;
+}
+
+hipError_t launch_adr_pair(int real_bytes, int ns, const AdrArgs<float> &af,
+                           const AdrArgs<double> &ad, hipStream_t s)
+{
+    return real_bytes == 4 ? pair_dispatch(ns, af, s) : pair_dispatch(ns, ad, s);
+}
 
 hipError_t launch_adr_step(int real_bytes, int ns, bool trace, const AdrArgs<float> &af,
                            const AdrArgs<double> &ad, hipStream_t s)

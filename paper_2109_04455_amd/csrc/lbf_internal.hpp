@@ -106,6 +106,11 @@ hipError_t launch_velocity_handoff(int real_bytes, const void *u, void *ua, cons
                                    double vel_scale, size_t plane, hipStream_t s);
 hipError_t launch_adr_init(int real_bytes, int ns, const AdrArgs<float> &af,
                            const AdrArgs<double> &ad, hipStream_t s);
+// Two ADR steps in one launch (temporal blocking through LDS, no trace); the
+// argument blocks carry the launch of pair_tile's tile shape.
+hipError_t launch_adr_pair(int real_bytes, int ns, const AdrArgs<float> &af,
+                           const AdrArgs<double> &ad, hipStream_t s);
+void pair_tile(int real_bytes, int &tx, int &ty);
 hipError_t launch_adr_step(int real_bytes, int ns, bool trace, const AdrArgs<float> &af,
                            const AdrArgs<double> &ad, hipStream_t s);
 hipError_t launch_flux(int real_bytes, int ns, const void *src, const uint8_t *mask5, int nx, int ny,

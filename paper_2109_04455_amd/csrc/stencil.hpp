@@ -11,7 +11,7 @@ namespace lbf {
 // 8 XCDs round-robin (block h runs on XCD h mod 8); with xcd_remap the
 // blocks of XCD j are given one contiguous range of tiles, so tiles that
 // share halo cache lines mostly run under the same L2.
-__device__ __forceinline__ void tile_coords(const Launch &L, int &x, int &y)
+__device__ __forceinline__ void tile_of_block(const Launch &L, int &bx, int &by)
 {
     const int nb = L.gx * L.gy;
     const int h = blockIdx.x;
@@ -20,7 +20,14 @@ __device__ __forceinline__ void tile_coords(const Launch &L, int &x, int &y)
         const int q = nb >> 3, r = nb & 7, j = h & 7, k = h >> 3;
         logical = j * q + (j < r ? j : r) + k;
     }
-    const int bx = logical % L.gx, by = logical / L.gx;
+    bx = logical % L.gx;
+    by = logical / L.gx;
+}
+
+__device__ __forceinline__ void tile_coords(const Launch &L, int &x, int &y)
+{
+    int bx, by;
+    tile_of_block(L, bx, by);
     const int t = threadIdx.x;
     x = bx * L.tx + t % L.tx;
     y = by * L.ty + t / L.tx;
@@ -66,6 +73,7 @@ struct PopBlock;
 
 template <typename Real, bool NT>
 struct PopBlock<Real, NT, false> {
+    using real_type = Real;
     rsrc_t r;
     __device__ __forceinline__ PopBlock(const Real *base, uint32_t bytes)
         : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<Real *>(base), 0, (int)bytes, 0x00020000))
@@ -93,6 +101,7 @@ struct PopBlock<Real, NT, false> {
 
 template <typename Real, bool NT>
 struct PopBlock<Real, NT, true> {
+    using real_type = Real;
     const char *p;
     __device__ __forceinline__ PopBlock(const Real *base, size_t)
         : p(reinterpret_cast<const char *>(base))
@@ -105,6 +114,17 @@ struct PopBlock<Real, NT, true> {
     __device__ __forceinline__ void store(size_t off, Real v) const
     {
         st<NT>(reinterpret_cast<Real *>(const_cast<char *>(p) + off), v);
+    }
+};
+
+// Populations of a tile held in LDS, addressed like a PopBlock.
+template <typename Real>
+struct LdsBlock {
+    using real_type = Real;
+    const Real *base;
+    __device__ __forceinline__ Real load(uint32_t off) const
+    {
+        return *reinterpret_cast<const Real *>(reinterpret_cast<const char *>(base) + off);
     }
 };
 

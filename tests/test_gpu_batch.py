@@ -19,8 +19,9 @@ def _params(w, real="f32", **kw):
 
 
 def _single(w, flow_steps, adr_steps, real="f32"):
+    # one step per launch (flags bit 8), the node update the batch runs
     import paper_2109_04455_amd as L
-    c = L.Context(_params(w, real, variant=1, tile_x=256, tile_y=1))
+    c = L.Context(_params(w, real, variant=1, tile_x=256, tile_y=1, flags=256))
     c.set_geometry(w.node_type)
     c.set_rates(w.k)
     c.flow_init()

@@ -168,10 +168,12 @@ def test_odd_width_fp64_parity():
 
 
 # --------------------------------------------------- execution-path checks
-def test_graph_replay_equals_direct_launches():
+@pytest.mark.parametrize("flags", [0, 256])
+def test_graph_replay_equals_direct_launches(flags):
+    # flags bit 8: one ADR step per launch (default: two-step launches)
     w = make_workload("tiny", real="f32")
-    a = _ctx(w)
-    b = _ctx(w)
+    a = _ctx(w, flags=flags)
+    b = _ctx(w, flags=flags)
     for c in (a, b):
         c.flow_init()
         c.flow_run(500)
@@ -223,11 +225,12 @@ def test_error_paths_on_device():
 
 @pytest.mark.parametrize("name,real", [("C2q", "f32"), ("tiny", "f64"), ("C1q", "f32")])
 def test_vectorised_kernel_equals_one_node_per_thread(name, real):
-    # variant 2: 16-byte vectors of nodes per thread; variant 1: one node per thread
+    # variant 2: 16-byte vectors of nodes per thread; variant 1: one node per
+    # thread (flags bit 8: every step runs the one-step kernel of the variant)
     w = make_workload(name)
     out = []
     for variant in (2, 1):
-        c = _ctx(w, real, variant=variant)
+        c = _ctx(w, real, variant=variant, flags=256)
         c.flow_init()
         c.flow_run(300)
         c.adr_init()
@@ -271,3 +274,29 @@ def test_32bit_and_64bit_population_offsets_agree(real):
         c.close()
     for a, b in zip(*out):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("name,real", [("tiny", "f32"), ("C1q", "f32"), ("C2q", "f32"),
+                                       ("tiny", "f64"), ("C1q", "f64")])
+def test_two_step_launches_equal_single_steps(name, real):
+    # untraced ADR steps run two per launch through LDS unless flags bit 8 is
+    # set; a block of any length ends in a single step.  The node arithmetic
+    # is the same code: FP32 storage agrees to rounding (bit for bit in
+    # practice), FP64 to a few ulps (multiply-adds are fused per kernel)
+    w = make_workload(name)
+    out = []
+    for flags in (0, 256):
+        c = _ctx(w, real, flags=flags)
+        c.flow_init()
+        c.flow_run(200)
+        c.adr_init()
+        for n in (1, 2, 3, 4, 7, 9, 300, 1001):
+            c.adr_run(n, check_every=n, tol=0)
+        assert c.adr_steps() == 1327
+        eps, N, inflow = c.efficiency()
+        out.append(([c.concentration(s).double() for s in range(w.nspecies)], np.asarray(N), inflow))
+        c.close()
+    tol = 1e-6 if real == "f32" else 1e-12
+    for a, b in zip(out[0][0], out[1][0]):
+        assert (a - b).abs().max().item() <= tol * b.abs().max().item()
+    assert np.abs(out[0][1] - out[1][1]).max() <= tol * abs(out[1][2])
