@@ -192,6 +192,21 @@ __device__ __forceinline__ void collide_react(const AdrArgs<Real> &a, size_t id,
     }
 }
 
+// Store the post-collision populations of node id.
+template <typename Real, typename Acc, int S, bool NT, bool WIDE>
+__device__ __forceinline__ void store_node(const AdrArgs<Real> &a, size_t id, const Acc (&h)[S][5])
+{
+    using Off = off_t_<WIDE>;
+    constexpr Off B = sizeof(Real);
+    const Off PB = (Off)a.plane * B, o = (Off)id * B;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const PopBlock<Real, NT, WIDE> out(a.dst + (size_t)s * 5 * a.plane, 5 * PB);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) out.store(o + i * PB, Real(h[s][i]));
+    }
+}
+
 // Collide + react + store for one node given its gathered populations.
 template <typename Real, typename Acc, int S, bool TRACE, bool NT, bool WIDE>
 __device__ __forceinline__ void collide_react_store(const AdrArgs<Real> &a, size_t id, unsigned m,
@@ -202,12 +217,7 @@ __device__ __forceinline__ void collide_react_store(const AdrArgs<Real> &a, size
     const Off PB = (Off)a.plane * B, o = (Off)id * B;
     const PopBlock<Real, false, WIDE> vel(a.ua, 2 * PB);
     collide_react<Real, Acc, S, TRACE>(a, id, m, Acc(vel.load(o)), Acc(vel.load(o + PB)), h);
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        const PopBlock<Real, NT, WIDE> out(a.dst + (size_t)s * 5 * a.plane, 5 * PB);
-#pragma unroll
-        for (int i = 0; i < 5; ++i) out.store(o + i * PB, Real(h[s][i]));
-    }
+    store_node<Real, Acc, S, NT, WIDE>(a, id, h);
 }
 
 // Full update of node (x, y): gather, collide, react, store.

@@ -141,6 +141,23 @@ __global__ __launch_bounds__(1024) void k_adr_step(AdrArgs<Real> a)
     adr::node_update<Real, Acc, S, TRACE, NT, WIDE>(a, x, y);
 }
 
+// Extended tile of the two-step kernel: 66 x EY nodes around 64 x (EY - 2)
+// output nodes.  EY = 15 for FP32 storage: 16 wavefronts and 58 KB of LDS per
+// block, two blocks per CU when a wavefront holds at most 64 VGPRs (OCC = 8
+// wavefronts per SIMD; one block per CU otherwise).  FP64: EY = 10, 11
+// wavefronts and 77 KB, two blocks per CU (6 wavefronts per SIMD).  Measured
+// on a 4096 x 1024 channel against EY = 6 .. 12 (FP32) and 4 .. 8 (FP64).
+template <typename Real>
+struct PairTile {
+    static constexpr int EY = sizeof(Real) == 4 ? 15 : 10;
+    static constexpr int OCC = sizeof(Real) == 4 ? 8 : 6;
+    // masks and velocities of the tile in LDS too (FP32: 67 KB per block)
+    static constexpr bool ULDS = sizeof(Real) == 4;
+    // streaming hint on the step-1 loads
+    static constexpr bool NTL = false;
+    static constexpr int TX = 64, TY = EY - 2;  // output nodes per block
+};
+
 // Two steps per launch (temporal blocking).  A block owns 64 x (EY - 2)
 // output nodes (rows aligned to 64 nodes) and the extended tile of 66 x EY
 // nodes around them (a ring of one node).  Step 1 updates the extended tile
@@ -151,12 +168,19 @@ __global__ __launch_bounds__(1024) void k_adr_step(AdrArgs<Real> a)
 // writes them.  A ring node is computed by every block whose tile it borders;
 // its source reads mostly hit the L2 that the XCD-aware block order shares
 // between neighbouring tiles.  The lattice crosses HBM once per two steps.
-// NTL: streaming hint on the step-1 loads; NT: on the final stores.
-template <typename Real, typename Acc, int S, bool NTL, bool NT, bool WIDE, int EY>
-__global__ __launch_bounds__(64 * (EY + 1)) void k_adr_step2(AdrArgs<Real> a)
+// Tile shape, occupancy target, the cache hint of the step-1 loads and
+// whether masks and velocities stay in LDS (step 2 then reads global memory
+// only for reaction rates) come from PairTile.  NT: streaming hint on the
+// final stores.
+template <typename Real, typename Acc, int S, bool NT, bool WIDE>
+__global__ __launch_bounds__(64 * (PairTile<Real>::EY + 1))
+__attribute__((amdgpu_waves_per_eu(PairTile<Real>::OCC))) void k_adr_step2(AdrArgs<Real> a)
 {
-    constexpr int EX = 66, TY = EY - 2, EP = EX * EY;
+    constexpr int EY = PairTile<Real>::EY, EX = 66, TY = EY - 2, EP = EX * EY;
+    constexpr bool ULDS = PairTile<Real>::ULDS;
     __shared__ Real lds[5 * S * EP];
+    __shared__ Real lvel[ULDS ? 2 * EP : 1];
+    __shared__ uint8_t lmask[ULDS ? EP : 1];
     using Off = off_t_<WIDE>;
     constexpr Off B = sizeof(Real);
     int bx, by;
@@ -177,22 +201,29 @@ __global__ __launch_bounds__(64 * (EY + 1)) void k_adr_step2(AdrArgs<Real> a)
         const int x = x0 - 1 + ex, y = y0 - 1 + ey;
         const bool inside = ey < EY && x >= 0 && x < a.nx && y >= 0 && y < a.ny;
         const size_t id = (size_t)y * a.nxp + x;
-        const unsigned m = inside ? a.mask5[id] : MASK5_SOLID;
-        if (m != MASK5_SOLID) {
+        const int e = ey * EX + ex;
+        if (inside) {
+            const unsigned m = a.mask5[id];
+            const Off PB = (Off)P * B, o = (Off)id * B;
+            const PopBlock<Real, false, WIDE> vel(a.ua, 2 * PB);
+            const Real u = vel.load(o), v = vel.load(o + PB);
             Acc h[S][5];
 #pragma unroll
             for (int s = 0; s < S; ++s)
-                adr::pull5<Real, Acc, NTL, WIDE>(a.src + (size_t)s * 5 * P, P, id, x, a.nx, a.nxp,
-                                                 m, s == 0, inlet_e, h[s]);
-            const Off PB = (Off)P * B, o = (Off)id * B;
-            const PopBlock<Real, false, WIDE> vel(a.ua, 2 * PB);
-            adr::collide_react<Real, Acc, S, false>(a, id, m, Acc(vel.load(o)),
-                                                    Acc(vel.load(o + PB)), h);
-            const int e = ey * EX + ex;
+                adr::pull5<Real, Acc, PairTile<Real>::NTL, WIDE>(
+                    a.src + (size_t)s * 5 * P, P, id, x, a.nx, a.nxp, m, s == 0, inlet_e, h[s]);
+            if (ULDS) {
+                lmask[e] = (uint8_t)m;
+                lvel[e] = u;
+                lvel[EP + e] = v;
+            }
+            if (m != MASK5_SOLID) {
+                adr::collide_react<Real, Acc, S, false>(a, id, m, Acc(u), Acc(v), h);
 #pragma unroll
-            for (int s = 0; s < S; ++s)
+                for (int s = 0; s < S; ++s)
 #pragma unroll
-                for (int i = 0; i < 5; ++i) lds[(s * 5 + i) * EP + e] = Real(h[s][i]);
+                    for (int i = 0; i < 5; ++i) lds[(s * 5 + i) * EP + e] = Real(h[s][i]);
+            }
         }
     }
     __syncthreads();
@@ -204,16 +235,22 @@ __global__ __launch_bounds__(64 * (EY + 1)) void k_adr_step2(AdrArgs<Real> a)
     const int x = x0 + lane, y = y0 + w;
     if (x >= a.nx || y >= a.ny) return;
     const size_t id = (size_t)y * a.nxp + x;
-    const unsigned m = a.mask5[id];
+    const int e = (w + 1) * EX + lane + 1;
+    const unsigned m = ULDS ? lmask[e] : a.mask5[id];
     if (m == MASK5_SOLID) return;
     constexpr uint32_t LB = sizeof(Real);
-    const uint32_t e = (uint32_t)((w + 1) * EX + lane + 1) * LB;
     Acc h[S][5];
 #pragma unroll
     for (int s = 0; s < S; ++s)
         adr::pull5_at<Acc>(LdsBlock<Real>{lds + s * 5 * EP}, (uint32_t)(EP * LB),
-                           (uint32_t)(EX * LB), e, x, a.nx, m, s == 0, inlet_e, h[s]);
-    adr::collide_react_store<Real, Acc, S, false, NT, WIDE>(a, id, m, h);
+                                 (uint32_t)(EX * LB), (uint32_t)e * LB, x, a.nx, m, s == 0,
+                                 inlet_e, h[s]);
+    if (ULDS) {
+        adr::collide_react<Real, Acc, S, false>(a, id, m, Acc(lvel[e]), Acc(lvel[EP + e]), h);
+        adr::store_node<Real, Acc, S, NT, WIDE>(a, id, h);
+    } else {
+        adr::collide_react_store<Real, Acc, S, false, NT, WIDE>(a, id, m, h);
+    }
 }
 
 // Reaction variant and/or periodic box (FP64 arithmetic, no trace).
@@ -514,27 +551,16 @@ hipError_t step_dispatch(int ns, bool trace, const AdrArgs<Real> &a, hipStream_t
     return hipGetLastError();
 }
 
-// Extended tile of the two-step kernel: 66 x EY nodes around 64 x (EY - 2)
-// output nodes.  EY = 15 for FP32 storage (16 wavefronts and 58 KB of LDS per
-// block, two blocks per CU); 10 for FP64 (11 wavefronts, 77 KB).  Measured on
-// a 4096 x 1024 channel against EY = 6 .. 12 (FP32) and 4 .. 8 (FP64).
-template <typename Real>
-struct PairTile {
-    static constexpr int EY = sizeof(Real) == 4 ? 15 : 10;
-    static constexpr int TX = 64, TY = EY - 2;  // output nodes per block
-};
-
 template <typename Real, typename Acc, int S>
 void pair_launch(const AdrArgs<Real> &a, hipStream_t s)
 {
-    constexpr int EY = PairTile<Real>::EY;
-    const dim3 g = a.L.grid(), b(64 * (EY + 1));
+    const dim3 g = a.L.grid(), b(64 * (PairTile<Real>::EY + 1));
     const int sel = (a.L.nontemporal ? 1 : 0) | (a.L.wide ? 2 : 0);
     switch (sel) {
-    case 0: hipLaunchKernelGGL((k_adr_step2<Real, Acc, S, false, false, false, EY>), g, b, 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_adr_step2<Real, Acc, S, false, true, false, EY>), g, b, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_adr_step2<Real, Acc, S, false, false, true, EY>), g, b, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_adr_step2<Real, Acc, S, false, true, true, EY>), g, b, 0, s, a); break;
+    case 0: hipLaunchKernelGGL((k_adr_step2<Real, Acc, S, false, false>), g, b, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_adr_step2<Real, Acc, S, true, false>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_adr_step2<Real, Acc, S, false, true>), g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_adr_step2<Real, Acc, S, true, true>), g, b, 0, s, a); break;
     }
 }
 
