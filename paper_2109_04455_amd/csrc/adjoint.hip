@@ -281,6 +281,25 @@ hipError_t forward_step(Ctx *c, const void *src, void *dst, void *trace, hipStre
     return launch_adr_step(c->p.real_bytes, c->p.nspecies, trace != nullptr, af, ad, s);
 }
 
+// Two forward steps from `src` into `dst` (two-step launch), recording the
+// trace of each step into its slot when given.
+hipError_t forward_pair(Ctx *c, const void *src, void *dst, void *trace1, void *trace2,
+                        hipStream_t s)
+{
+    AdrArgs<float> af = adr_args<float>(c, 0);
+    AdrArgs<double> ad = adr_args<double>(c, 0);
+    af.src = (const float *)src;
+    af.dst = (float *)dst;
+    af.trace = (float *)trace1;
+    af.trace2 = (float *)trace2;
+    ad.src = (const double *)src;
+    ad.dst = (double *)dst;
+    ad.trace = (double *)trace1;
+    ad.trace2 = (double *)trace2;
+    af.L = ad.L = c->Lp;
+    return launch_adr_pair(c->p.real_bytes, c->p.nspecies, af, ad, s);
+}
+
 struct AdjLayout {
     size_t nu[2], rec[2], ckpt, ckpt_trace, trace, acc, partial, total;
     long nseg;
@@ -383,21 +402,29 @@ lbf_status lbf_adr_adjoint(lbf_ctx c, long T, int M, int keep, void *ws, size_t 
     // the last segment's trace is recorded here directly into the segment
     // trace buffer, which the reverse sweep visits first: no recompute for it
     const long last_a0 = (L.nseg - 1) * (long)M;
-    for (long m = 1; m <= T; ++m) {
-        void *tr = nullptr;
-        if (keep) {
-            if (m < T) tr = slot(L.trace, m);
-        } else if (m % M == 0 && m < T) {
-            tr = slot(L.ckpt_trace, m / M);
-        } else if (m > last_a0 && m < T) {
-            tr = slot(L.trace, m - last_a0);
-        }
-        e = enqueue_adr_step(c, c->gpar, s, tr);
+    auto trace_of = [&](long m) -> void * {
+        if (m >= T) return nullptr;
+        if (keep) return slot(L.trace, m);
+        if (m % M == 0) return slot(L.ckpt_trace, m / M);
+        if (m > last_a0) return slot(L.trace, m - last_a0);
+        return nullptr;
+    };
+    auto ckpt_after = [&](long m) { return !keep && m % M == 0 && m < T; };
+    // steps run two per launch where no checkpoint falls between them; the
+    // last step is a single one (the outlet fluxes read the state before it)
+    for (long m = 1; m <= T;) {
+        const bool two = c->pair && m + 1 < T && !ckpt_after(m);
+        if (two)
+            e = forward_pair(c, c->ptr(c->off.g[c->gpar]), c->ptr(c->off.g[c->gpar ^ 1]),
+                             trace_of(m), trace_of(m + 1), s);
+        else
+            e = enqueue_adr_step(c, c->gpar, s, trace_of(m));
         if (e != hipSuccess) return hip_fail(c, e, "forward step");
         c->gpar ^= 1;
-        if (!keep && m % M == 0 && m < T) {
-            e = hipMemcpyAsync(W + L.ckpt + (size_t)(m / M) * L.lattice, c->ptr(c->off.g[c->gpar]),
-                               L.lattice, hipMemcpyDeviceToDevice, s);
+        m += two ? 2 : 1;
+        if (ckpt_after(m - 1)) {
+            e = hipMemcpyAsync(W + L.ckpt + (size_t)((m - 1) / M) * L.lattice,
+                               c->ptr(c->off.g[c->gpar]), L.lattice, hipMemcpyDeviceToDevice, s);
             if (e != hipSuccess) return hip_fail(c, e, "checkpoint copy");
         }
     }
@@ -441,11 +468,14 @@ lbf_status lbf_adr_adjoint(lbf_ctx c, long T, int M, int keep, void *ws, size_t 
             if (e != hipSuccess) return hip_fail(c, e, "segment trace copy");
             const void *src = W + L.ckpt + (size_t)j * L.lattice;
             int r = 0;
-            for (long q = 1; q < a1 - a0 && j < L.nseg - 1; ++q) {
-                e = forward_step(c, src, rec[r], slot(L.trace, q), s);
+            for (long q = 1; q < a1 - a0 && j < L.nseg - 1;) {
+                const bool two = c->pair && q + 1 < a1 - a0;
+                e = two ? forward_pair(c, src, rec[r], slot(L.trace, q), slot(L.trace, q + 1), s)
+                        : forward_step(c, src, rec[r], slot(L.trace, q), s);
                 if (e != hipSuccess) return hip_fail(c, e, "recompute step");
                 src = rec[r];
                 r ^= 1;
+                q += two ? 2 : 1;
             }
             for (long m = a1 - 1; m >= a0; --m) {
                 e = launch_adjoint_step(c, nu[cur], nu[cur ^ 1], slot(L.trace, m - a0), acc, s);

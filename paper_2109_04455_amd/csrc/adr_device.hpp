@@ -122,7 +122,7 @@ __device__ __forceinline__ void eq_factors(Acc u, Acc v, Acc (&p)[5])
 }
 
 // Collide + react one node given its gathered populations (in place);
-// records (C_A, C_B) at trace nodes when TRACE.  MODE 0: link reaction, only
+// records (C_A, C_B) at trace nodes when TRACE and a.trace is set.  MODE 0: link reaction, only
 // the population heading into a catalytic node reacts (rate of that node);
 // MODE 1: the paper's comparison variant, every population of a fluid node
 // next to catalysts reacts, with the mean rate of its catalytic neighbours of
@@ -184,7 +184,7 @@ __device__ __forceinline__ void collide_react(const AdrArgs<Real> &a, size_t id,
                 }
             }
         }
-        if (TRACE) {
+        if (TRACE && a.trace) {
             const int t = a.trace_idx[id];
             a.trace[2 * t] = Real(c[0]);
             a.trace[2 * t + 1] = S == 3 ? Real(c[1]) : Real(0);
@@ -269,6 +269,121 @@ __device__ __forceinline__ void node_update_ext(const AdrArgs<Real> &a, int x, i
     for (int s = 0; s < S; ++s)
 #pragma unroll
         for (int i = 0; i < 5; ++i) st<NT>(a.dst + (s * 5 + i) * P + id, Real(h[s][i]));
+}
+
+// Extended tile of the two-step kernel: 66 x EY nodes around 64 x (EY - 2)
+// output nodes.  EY = 15 for FP32 storage: 16 wavefronts and 58 KB of LDS per
+// block, two blocks per CU when a wavefront holds at most 64 VGPRs (OCC = 8
+// wavefronts per SIMD; one block per CU otherwise).  FP64: EY = 10, 11
+// wavefronts and 77 KB, two blocks per CU (6 wavefronts per SIMD).  Measured
+// on a 4096 x 1024 channel against EY = 6 .. 12 (FP32) and 4 .. 8 (FP64).
+template <typename Real>
+struct PairTile {
+    static constexpr int EY = sizeof(Real) == 4 ? 15 : 10;
+    static constexpr int OCC = sizeof(Real) == 4 ? 8 : 6;
+    // masks and velocities of the tile in LDS too (FP32: 67 KB per block)
+    static constexpr bool ULDS = sizeof(Real) == 4;
+    // streaming hint on the step-1 loads
+    static constexpr bool NTL = false;
+    static constexpr int TX = 64, TY = EY - 2;  // output nodes per block
+};
+
+// Two steps per launch (temporal blocking).  A block owns 64 x (EY - 2)
+// output nodes (rows aligned to 64 nodes) and the extended tile of 66 x EY
+// nodes around them (a ring of one node).  Step 1 updates the extended tile
+// from the lattice in HBM and keeps the result in LDS, rounded to Real
+// exactly as a store to HBM would round it: wavefront w < EY takes the 64
+// core nodes of extended row w, wavefront EY the two ring columns of every
+// row.  Step 2 gathers the output nodes from LDS, one row per wavefront, and
+// writes them.  A ring node is computed by every block whose tile it borders;
+// its source reads mostly hit the L2 that the XCD-aware block order shares
+// between neighbouring tiles.  The lattice crosses HBM once per two steps.
+// Tile shape, occupancy target, the cache hint of the step-1 loads and
+// whether masks and velocities stay in LDS (step 2 then reads global memory
+// only for reaction rates) come from PairTile.  NT: streaming hint on the
+// final stores.  Callers launch 64 x (EY + 1) threads per block.
+template <typename Real, typename Acc, int S, bool NT, bool WIDE, bool TRACE>
+__device__ __forceinline__ void pair_update(const AdrArgs<Real> &a, int bx, int by)
+{
+    constexpr int EY = PairTile<Real>::EY, EX = 66, TY = EY - 2, EP = EX * EY;
+    constexpr bool ULDS = PairTile<Real>::ULDS;
+    __shared__ Real lds[5 * S * EP];
+    __shared__ Real lvel[ULDS ? 2 * EP : 1];
+    __shared__ uint8_t lmask[ULDS ? EP : 1];
+    using Off = off_t_<WIDE>;
+    constexpr Off B = sizeof(Real);
+    const int x0 = bx * 64, y0 = by * TY;  // first output node
+    const int w = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
+    const size_t P = a.plane;
+    const Acc inlet_e = Acc(2) * w5<Acc>(DE) * (Acc(a.cin) - Acc(a.cref));
+    {
+        int ex, ey;
+        if (w < EY) {
+            ey = w;
+            ex = lane + 1;
+        } else {
+            ey = lane >> 1;
+            ex = (lane & 1) ? EX - 1 : 0;
+        }
+        const int x = x0 - 1 + ex, y = y0 - 1 + ey;
+        const bool inside = ey < EY && x >= 0 && x < a.nx && y >= 0 && y < a.ny;
+        const size_t id = (size_t)y * a.nxp + x;
+        const int e = ey * EX + ex;
+        if (inside) {
+            const unsigned m = a.mask5[id];
+            const Off PB = (Off)P * B, o = (Off)id * B;
+            const PopBlock<Real, false, WIDE> vel(a.ua, 2 * PB);
+            const Real u = vel.load(o), v = vel.load(o + PB);
+            Acc h[S][5];
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                pull5<Real, Acc, PairTile<Real>::NTL, WIDE>(
+                    a.src + (size_t)s * 5 * P, P, id, x, a.nx, a.nxp, m, s == 0, inlet_e, h[s]);
+            if (ULDS) {
+                lmask[e] = (uint8_t)m;
+                lvel[e] = u;
+                lvel[EP + e] = v;
+            }
+            if (m != MASK5_SOLID) {
+                // step-1 concentrations are recorded by the block owning the node
+                AdrArgs<Real> a1 = a;
+                const bool own = ex >= 1 && ex <= 64 && ey >= 1 && ey <= TY;
+                a1.trace = own ? a.trace : nullptr;
+                collide_react<Real, Acc, S, TRACE>(a1, id, m, Acc(u), Acc(v), h);
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+#pragma unroll
+                    for (int i = 0; i < 5; ++i) lds[(s * 5 + i) * EP + e] = Real(h[s][i]);
+            }
+        }
+    }
+    __syncthreads();
+    // Step 2 on the output rows.  The ring nodes a gather can reach (x - 1
+    // for x > 0, x + 1 for x < nx - 1, y +- 1 of a fluid node) were all
+    // updated above; ring nodes outside the lattice are never read (inlet and
+    // outlet rules, solid channel walls).
+    if (w >= TY) return;
+    const int x = x0 + lane, y = y0 + w;
+    if (x >= a.nx || y >= a.ny) return;
+    const size_t id = (size_t)y * a.nxp + x;
+    const int e = (w + 1) * EX + lane + 1;
+    const unsigned m = ULDS ? lmask[e] : a.mask5[id];
+    if (m == MASK5_SOLID) return;
+    constexpr uint32_t LB = sizeof(Real);
+    Acc h[S][5];
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+        pull5_at<Acc>(LdsBlock<Real>{lds + s * 5 * EP}, (uint32_t)(EP * LB),
+                                 (uint32_t)(EX * LB), (uint32_t)e * LB, x, a.nx, m, s == 0,
+                                 inlet_e, h[s]);
+    AdrArgs<Real> a2 = a;
+    a2.trace = a.trace2;
+    if (ULDS) {
+        collide_react<Real, Acc, S, TRACE>(a2, id, m, Acc(lvel[e]), Acc(lvel[EP + e]), h);
+        store_node<Real, Acc, S, NT, WIDE>(a2, id, h);
+    } else {
+        collide_react_store<Real, Acc, S, TRACE, NT, WIDE>(a2, id, m, h);
+    }
 }
 
 }  // namespace adr

@@ -27,7 +27,8 @@ template <typename Real>
 struct Inst {
     AdrArgs<Real> adr;
     FlowArgs<Real> flow;
-    int tiles_x, tiles_y;  // tile grid of this instance
+    int tiles_x, tiles_y;    // tile grid of this instance (one-step kernels)
+    int ptiles_x, ptiles_y;  // tile grid of the two-step kernel
     int xf;
     double cin, cref;
 };
@@ -110,17 +111,24 @@ __global__ __launch_bounds__(256) void k_batch_flow(const Inst<Real> *insts, con
     }
 }
 
-// Rebuild the tile table from the per-instance active flags (one block).
+// Rebuild a tile table from the per-instance active flags (one block): the
+// one-step tiles, or with `pair` the tiles of the two-step kernel.
 template <typename Real>
-__global__ void k_build_tiles(const Inst<Real> *insts, const int *active, int n, int4 *tiles,
-                              int *ntiles)
+__global__ void k_build_tiles(const Inst<Real> *insts, const int *active, int n, bool pair,
+                              int4 *tiles, int *ntiles)
 {
     __shared__ int base[1025];
+    auto grid_of = [&](int i, int &gx, int &gy) {
+        gx = pair ? insts[i].ptiles_x : insts[i].tiles_x;
+        gy = pair ? insts[i].ptiles_y : insts[i].tiles_y;
+    };
     if (threadIdx.x == 0) {
         int acc = 0;
         for (int i = 0; i < n; ++i) {
             base[i] = acc;
-            if (active[i]) acc += insts[i].tiles_x * insts[i].tiles_y;
+            int gx, gy;
+            grid_of(i, gx, gy);
+            if (active[i]) acc += gx * gy;
         }
         base[n] = acc;
         *ntiles = acc;
@@ -128,10 +136,26 @@ __global__ void k_build_tiles(const Inst<Real> *insts, const int *active, int n,
     __syncthreads();
     for (int i = 0; i < n; ++i) {
         if (!active[i]) continue;
-        const int tx = insts[i].tiles_x, cnt = tx * insts[i].tiles_y;
-        for (int k = threadIdx.x; k < cnt; k += blockDim.x)
-            tiles[base[i] + k] = make_int4(i, k % tx, k / tx, 0);
+        int gx, gy;
+        grid_of(i, gx, gy);
+        for (int k = threadIdx.x; k < gx * gy; k += blockDim.x)
+            tiles[base[i] + k] = make_int4(i, k % gx, k / gx, 0);
     }
+}
+
+// Two steps of every active instance per launch: one block per slot of the
+// two-step tile table (slots past the live count exit at once), each block
+// the two-step tile update of the single-lattice path.
+template <typename Real, int S, bool NT, bool WIDE>
+__global__ __launch_bounds__(64 * (adr::PairTile<Real>::EY + 1))
+__attribute__((amdgpu_waves_per_eu(adr::PairTile<Real>::OCC)))
+void k_batch_adr2(const Inst<Real> *insts, const int4 *tiles, const int *ntiles, int parity)
+{
+    if ((int)blockIdx.x >= *ntiles) return;
+    const int4 T = tiles[blockIdx.x];
+    AdrArgs<Real> a = insts[T.x].adr;
+    swap_parity(a, parity);
+    adr::pair_update<Real, double, S, NT, WIDE, false>(a, T.y, T.z);
 }
 
 // Outlet and inlet fluxes of every instance (one block per instance, the
@@ -208,6 +232,9 @@ struct lbf_batch_s {
     std::vector<lbf_params> p;
     std::vector<Ctx> ctx;  // per-instance layout and argument builders (no own workspace)
     std::vector<size_t> base;  // byte offset of each instance's block
+    size_t off_ptiles = 0, off_nptiles = 0;  // tile table of the two-step kernel
+    int max_ptiles = 0;
+    bool pair = true;  // ADR steps two per launch (flags bit 8 of instance 0 clears it)
     size_t off_inst = 0, off_tiles = 0, off_ntiles = 0, off_active = 0, off_obs = 0, off_du = 0,
            off_uprevp = 0, total = 0;
     int max_tiles = 0;
@@ -249,6 +276,10 @@ void fill_insts(lbf_batch b, std::vector<Inst<Real>> &v)
         I.flow = flow_args<Real>(c, 0);
         I.tiles_x = (c->p.nx + b->tx - 1) / b->tx;
         I.tiles_y = (c->p.ny + b->ty - 1) / b->ty;
+        int ptx, pty;
+        pair_tile(c->p.real_bytes, ptx, pty);
+        I.ptiles_x = (c->p.nx + ptx - 1) / ptx;
+        I.ptiles_y = (c->p.ny + pty - 1) / pty;
         I.xf = c->xf;
         I.cin = c->p.c_in;
         I.cref = c->cref;
@@ -279,15 +310,20 @@ hipError_t set_active(lbf_batch b, const std::vector<int> &act)
     hipError_t e = hipMemcpyAsync(b->ws + b->off_active, act.data(), act.size() * sizeof(int),
                                   hipMemcpyHostToDevice, b->stream);
     if (e != hipSuccess) return e;
-    if (b->p[0].real_bytes == 4)
-        hipLaunchKernelGGL(k_build_tiles<float>, dim3(1), dim3(256), 0, b->stream,
-                           (const Inst<float> *)(b->ws + b->off_inst), (const int *)(b->ws + b->off_active),
-                           b->n, (int4 *)(b->ws + b->off_tiles), (int *)(b->ws + b->off_ntiles));
-    else
-        hipLaunchKernelGGL(k_build_tiles<double>, dim3(1), dim3(256), 0, b->stream,
-                           (const Inst<double> *)(b->ws + b->off_inst), (const int *)(b->ws + b->off_active),
-                           b->n, (int4 *)(b->ws + b->off_tiles), (int *)(b->ws + b->off_ntiles));
-    e = hipGetLastError();
+    for (int pair = 0; pair < 2 && e == hipSuccess; ++pair) {
+        int4 *tiles = (int4 *)(b->ws + (pair ? b->off_ptiles : b->off_tiles));
+        int *nt = (int *)(b->ws + (pair ? b->off_nptiles : b->off_ntiles));
+        const int *act_d = (const int *)(b->ws + b->off_active);
+        if (b->p[0].real_bytes == 4)
+            hipLaunchKernelGGL(k_build_tiles<float>, dim3(1), dim3(256), 0, b->stream,
+                               (const Inst<float> *)(b->ws + b->off_inst), act_d, b->n, pair != 0,
+                               tiles, nt);
+        else
+            hipLaunchKernelGGL(k_build_tiles<double>, dim3(1), dim3(256), 0, b->stream,
+                               (const Inst<double> *)(b->ws + b->off_inst), act_d, b->n, pair != 0,
+                               tiles, nt);
+        e = hipGetLastError();
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);  // act must outlive the copy
     return e;
 }
@@ -319,6 +355,58 @@ void batch_launch(lbf_batch b, int kind, int parity, bool write_u, hipStream_t s
     }
 }
 
+template <typename Real, bool NT, bool WIDE>
+void batch_pair_launch(lbf_batch b, int parity, hipStream_t s)
+{
+    const int4 *tiles = (const int4 *)(b->ws + b->off_ptiles);
+    const int *nt = (const int *)(b->ws + b->off_nptiles);
+    auto I = (const Inst<Real> *)(b->ws + b->off_inst);
+    const dim3 g(b->max_ptiles), blk(64 * (adr::PairTile<Real>::EY + 1));
+    if (b->p[0].nspecies == 2)
+        hipLaunchKernelGGL((k_batch_adr2<Real, 2, NT, WIDE>), g, blk, 0, s, I, tiles, nt, parity);
+    else
+        hipLaunchKernelGGL((k_batch_adr2<Real, 3, NT, WIDE>), g, blk, 0, s, I, tiles, nt, parity);
+}
+
+// Two ADR steps of every active instance in one launch.
+hipError_t enqueue_batch_pair(lbf_batch b, int parity, hipStream_t s)
+{
+    const int sel = (b->nontemporal ? 1 : 0) | (b->wide ? 2 : 0);
+    auto launch = [&](auto real) {
+        using Real = decltype(real);
+        switch (sel) {
+        case 0: batch_pair_launch<Real, false, false>(b, parity, s); break;
+        case 1: batch_pair_launch<Real, true, false>(b, parity, s); break;
+        case 2: batch_pair_launch<Real, false, true>(b, parity, s); break;
+        default: batch_pair_launch<Real, true, true>(b, parity, s); break;
+        }
+    };
+    if (b->p[0].real_bytes == 4)
+        launch(float(0));
+    else
+        launch(double(0));
+    return hipGetLastError();
+}
+
+hipError_t enqueue_batch_step(lbf_batch b, int kind, int parity, bool write_u, hipStream_t s);
+
+// ADR blocks run like the single-lattice path: floor((n - 1) / 2) two-step
+// launches, then single steps (the last step of a block is a single one).
+long batch_pairs(const lbf_batch_s *b, int kind, long n)
+{
+    return kind == KIND_ADR && b->pair && n >= 3 ? (n - 1) / 2 : 0;
+}
+
+hipError_t enqueue_batch_block(lbf_batch b, int kind, int &par, long n, hipStream_t s)
+{
+    const long pairs = batch_pairs(b, kind, n);
+    hipError_t e = hipSuccess;
+    for (long i = 0; i < pairs && e == hipSuccess; ++i, par ^= 1) e = enqueue_batch_pair(b, par, s);
+    for (long i = 2 * pairs; i < n && e == hipSuccess; ++i, par ^= 1)
+        e = enqueue_batch_step(b, kind, par, i == n - 1, s);
+    return e;
+}
+
 hipError_t enqueue_batch_step(lbf_batch b, int kind, int parity, bool write_u, hipStream_t s)
 {
     const int sel = (b->nontemporal ? 1 : 0) | (b->wide ? 2 : 0);
@@ -343,11 +431,8 @@ lbf_status batch_steps(lbf_batch b, int kind, long n)
 {
     int &par = kind == KIND_ADR ? b->gpar : b->fpar;
     if (n < GRAPH_MIN_STEPS) {
-        for (long i = 0; i < n; ++i) {
-            hipError_t e = enqueue_batch_step(b, kind, par, i == n - 1, b->stream);
-            if (e != hipSuccess) return bhip(b, e, "batched step");
-            par ^= 1;
-        }
+        hipError_t e = enqueue_batch_block(b, kind, par, n, b->stream);
+        if (e != hipSuccess) return bhip(b, e, "batched step");
         return LBF_OK;
     }
     const auto key = std::make_tuple(kind, n, par);
@@ -356,11 +441,7 @@ lbf_status batch_steps(lbf_batch b, int kind, long n)
         hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return bhip(b, e, "hipStreamBeginCapture");
         int p = par;
-        hipError_t le = hipSuccess;
-        for (long i = 0; i < n && le == hipSuccess; ++i) {
-            le = enqueue_batch_step(b, kind, p, i == n - 1, b->cap_stream);
-            p ^= 1;
-        }
+        const hipError_t le = enqueue_batch_block(b, kind, p, n, b->cap_stream);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(b->cap_stream, &g);
         if (le != hipSuccess) {
@@ -376,7 +457,7 @@ lbf_status batch_steps(lbf_batch b, int kind, long n)
     }
     hipError_t e = hipGraphLaunch(it->second, b->stream);
     if (e != hipSuccess) return bhip(b, e, "hipGraphLaunch");
-    if (n & 1) par ^= 1;
+    if ((n - batch_pairs(b, kind, n)) & 1) par ^= 1;
     return LBF_OK;
 }
 
@@ -461,10 +542,18 @@ lbf_status lbf_batch_create(int n, const lbf_params *params, lbf_batch *out)
         tiles += ((params[i].nx + b->tx - 1) / b->tx) * ((params[i].ny + b->ty - 1) / b->ty);
     }
     b->max_tiles = tiles;
+    int ptx, pty, ptiles = 0;
+    pair_tile(p0.real_bytes, ptx, pty);
+    for (int i = 0; i < n; ++i)
+        ptiles += ((params[i].nx + ptx - 1) / ptx) * ((params[i].ny + pty - 1) / pty);
+    b->max_ptiles = ptiles;
+    b->pair = !(p0.flags & 256);
     const size_t inst_bytes = p0.real_bytes == 4 ? sizeof(Inst<float>) : sizeof(Inst<double>);
     b->off_inst = take((size_t)n * inst_bytes);
     b->off_tiles = take((size_t)tiles * sizeof(int4));
     b->off_ntiles = take(sizeof(int));
+    b->off_ptiles = take((size_t)ptiles * sizeof(int4));
+    b->off_nptiles = take(sizeof(int));
     b->off_active = take((size_t)n * sizeof(int));
     b->off_obs = take((size_t)n * 4 * sizeof(double));
     b->off_du = take((size_t)n * sizeof(double));

@@ -73,7 +73,8 @@ struct AdrArgs {
     const uint8_t *type;
     const Real *kr;     // per-node rate (read at catalytic neighbours)
     const int32_t *trace_idx;  // per-node index into the trace list
-    Real *trace;        // [ntrace][2] concentrations (C_A, C_B) of this step
+    Real *trace;        // [ntrace][2] concentrations (C_A, C_B) of this step (or NULL)
+    Real *trace2;       // two-step launches: the same for the second step (or NULL)
     int nx, ny, nxp;
     size_t plane;
     double omega;       // 1 / tau_g
@@ -106,8 +107,9 @@ hipError_t launch_velocity_handoff(int real_bytes, const void *u, void *ua, cons
                                    double vel_scale, size_t plane, hipStream_t s);
 hipError_t launch_adr_init(int real_bytes, int ns, const AdrArgs<float> &af,
                            const AdrArgs<double> &ad, hipStream_t s);
-// Two ADR steps in one launch (temporal blocking through LDS, no trace); the
-// argument blocks carry the launch of pair_tile's tile shape.
+// Two ADR steps in one launch (temporal blocking through LDS); the argument
+// blocks carry the launch of pair_tile's tile shape and, optionally, the
+// trace slots of the two steps (trace, trace2).
 hipError_t launch_adr_pair(int real_bytes, int ns, const AdrArgs<float> &af,
                            const AdrArgs<double> &ad, hipStream_t s);
 void pair_tile(int real_bytes, int &tx, int &ty);
