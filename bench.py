@@ -182,6 +182,9 @@ def batch_leg(steps=2000, flow_steps=2000):
             "serial_mlups": round(nodes * steps / s["adr_seconds"] / 1e6, 1),
             "speedup": round(s["adr_seconds"] / b["adr_seconds"], 3),
             "batched_total_s": round(b["seconds"], 3), "serial_total_s": round(s["seconds"], 3),
+            "batched_flow_s": round(b["flow_seconds"], 3), "serial_flow_s": round(s["flow_seconds"], 3),
+            "batched_setup_s": round(b["setup_seconds"], 3),
+            "serial_setup_s": round(s["setup_seconds"], 3),
             "identical_results": same}
 
 def membrane3d_leg(steps=2000):

@@ -91,12 +91,18 @@ __global__ __launch_bounds__(256) void k_batch_adr(const Inst<Real> *insts, cons
     }
 }
 
-template <typename Real, bool WRITE_U, bool NT, bool WIDE>
+template <typename Real, bool WRITE_U, bool NT, bool WIDE, bool PERSIST>
 __global__ __launch_bounds__(256) void k_batch_flow(const Inst<Real> *insts, const int4 *tiles,
                                                     const int *ntiles, int parity, int tx, int ty)
 {
     int t0, t1;
-    chunk_of_block(*ntiles, t0, t1);
+    if (PERSIST) {
+        chunk_of_block(*ntiles, t0, t1);
+    } else {
+        // one block per table slot; slots past the live count exit at once
+        t0 = (int)blockIdx.x;
+        t1 = t0 < *ntiles ? t0 + 1 : t0;
+    }
     for (int t = t0; t < t1; ++t) {
         const int4 T = tiles[t];
         FlowArgs<Real> a = insts[T.x].flow;
@@ -348,10 +354,19 @@ void batch_launch(lbf_batch b, int kind, int parity, bool write_u, hipStream_t s
             else
                 hipLaunchKernelGGL((k_batch_adr<Real, 3, NT, false, WIDE>), ga, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
         }
-    } else if (write_u) {
-        hipLaunchKernelGGL((k_batch_flow<Real, true, NT, WIDE>), g, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
     } else {
-        hipLaunchKernelGGL((k_batch_flow<Real, false, NT, WIDE>), g, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
+        const dim3 gf(b->persistent ? b->grid : b->max_tiles);
+        if (b->persistent) {
+            if (write_u)
+                hipLaunchKernelGGL((k_batch_flow<Real, true, NT, WIDE, true>), gf, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
+            else
+                hipLaunchKernelGGL((k_batch_flow<Real, false, NT, WIDE, true>), gf, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
+        } else {
+            if (write_u)
+                hipLaunchKernelGGL((k_batch_flow<Real, true, NT, WIDE, false>), gf, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
+            else
+                hipLaunchKernelGGL((k_batch_flow<Real, false, NT, WIDE, false>), gf, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
+        }
     }
 }
 

@@ -16,12 +16,15 @@ def _params(w, **kw):
 
 def sweep_batched(instances, flow_steps, adr_steps, check_every=1000, tol=0.0, flow_tol=0.0,
                   tile=(256, 1), flags=0):
-    """Returns dict(eps, product_flux, steps, seconds, adr_seconds)."""
+    """Returns dict(eps, product_flux, steps, seconds, setup_seconds,
+    flow_seconds, adr_seconds)."""
     import paper_2109_04455_amd as L
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b = L.Batch([_params(w, tile_x=tile[0], tile_y=tile[1], flags=flags) for w in instances])
     b.set_geometry([w.node_type for w in instances], [w.k for w in instances])
+    torch.cuda.synchronize()
+    tf = time.perf_counter()
     b.flow(flow_steps, check_every=check_every, tol=flow_tol)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -30,7 +33,7 @@ def sweep_batched(instances, flow_steps, adr_steps, check_every=1000, tol=0.0, f
     t2 = time.perf_counter()
     b.close()
     return {"eps": eps, "product_flux": prod, "steps": steps, "seconds": t2 - t0,
-            "adr_seconds": t2 - t1}
+            "setup_seconds": tf - t0, "flow_seconds": t1 - tf, "adr_seconds": t2 - t1}
 
 
 def sweep_serial(instances, flow_steps, adr_steps, check_every=1000, tol=0.0, flow_tol=0.0,
@@ -39,17 +42,20 @@ def sweep_serial(instances, flow_steps, adr_steps, check_every=1000, tol=0.0, fl
     captured graphs."""
     import paper_2109_04455_amd as L
     eps, prod, steps = [], [], []
-    adr_s = 0.0
+    adr_s = flow_s = 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for w in instances:
         c = L.Context(_params(w, tile_x=tile[0], tile_y=tile[1], flags=flags))
         c.set_geometry(w.node_type)
         c.set_rates(w.k)
+        torch.cuda.synchronize()
+        tf = time.perf_counter()
         c.flow_init()
         c.flow_steady(flow_steps, check_every, flow_tol)
         torch.cuda.synchronize()
         ta = time.perf_counter()
+        flow_s += ta - tf
         c.adr_init()
         n, _ = c.adr_run(adr_steps, check_every=check_every, tol=tol)
         e, N, _ = c.efficiency()
@@ -59,5 +65,7 @@ def sweep_serial(instances, flow_steps, adr_steps, check_every=1000, tol=0.0, fl
         prod.append(N[-1])
         steps.append(n)
         c.close()
+    total = time.perf_counter() - t0
     return {"eps": np.array(eps), "product_flux": np.array(prod), "steps": np.array(steps),
-            "seconds": time.perf_counter() - t0, "adr_seconds": adr_s}
+            "seconds": total, "setup_seconds": total - flow_s - adr_s, "flow_seconds": flow_s,
+            "adr_seconds": adr_s}
