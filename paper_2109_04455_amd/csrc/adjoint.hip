@@ -53,7 +53,7 @@ struct AdjArgs {
 };
 
 // One adjoint step at node x for all species.
-template <typename Real, int S, bool NT>
+template <typename Real, int S, bool NT, bool WIDE>
 __global__ __launch_bounds__(1024) void k_adjoint_step(AdjArgs<Real> a)
 {
     int x, y;
@@ -63,32 +63,33 @@ __global__ __launch_bounds__(1024) void k_adjoint_step(AdjArgs<Real> a)
     const unsigned m = a.mask5[id];
     if (m == MASK5_SOLID) return;
     const size_t P = a.plane;
+    // byte offsets from each species' block, as in the forward gather
+    using Off = off_t_<WIDE>;
+    constexpr Off B = sizeof(Real);
+    const Off PB = (Off)P * B, RB = (Off)a.nxp * B, o = (Off)id * B;
+    const Off oE = o + DE * PB, oN = o + DN * PB, oW = o + DW * PB, oS = o + DS * PB;
     Real lam[S][5];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        const Real *nu = a.nu_src + (size_t)s * 5 * P;
-        lam[s][0] = ld<NT>(nu + id);
+        const PopBlock<Real, NT, WIDE> nu(a.nu_src + (size_t)s * 5 * P, 5 * PB);
+        lam[s][0] = nu.load(o);
         // z_E(x) feeds g_E(x+1), or g_W(x) by bounce-back, or the outlet rule
         if (x == a.nx - 1)
-            lam[s][DE] = -ld<NT>(nu + DW * P + id);
-        else if (m & BIT_E)
-            lam[s][DE] = ld<NT>(nu + DW * P + id);
+            lam[s][DE] = -nu.load(oW);
         else
-            lam[s][DE] = ld<NT>(nu + DE * P + id + 1);
-        lam[s][DN] = (m & BIT_N) ? ld<NT>(nu + DS * P + id) : ld<NT>(nu + DN * P + id + a.nxp);
+            lam[s][DE] = nu.load((m & BIT_E) ? oW : oE + B);
+        lam[s][DN] = nu.load((m & BIT_N) ? oS : oN + RB);
         // z_W(x) feeds g_W(x-1), or g_E(x) by bounce-back / the inlet rule
         if (x == 0)
-            lam[s][DW] = s == 0 ? -ld<NT>(nu + DE * P + id) : ld<NT>(nu + DE * P + id);
-        else if (m & BIT_W)
-            lam[s][DW] = ld<NT>(nu + DE * P + id);
+            lam[s][DW] = s == 0 ? -nu.load(oE) : nu.load(oE);
         else
-            lam[s][DW] = ld<NT>(nu + DW * P + id - 1);
-        lam[s][DS] = (m & BIT_S) ? ld<NT>(nu + DN * P + id) : ld<NT>(nu + DS * P + id - a.nxp);
+            lam[s][DW] = nu.load((m & BIT_W) ? oE : oW - B);
+        lam[s][DS] = nu.load((m & BIT_S) ? oN : oS - RB);
         if (x == a.nx - 1) {
             // outlet: every post-collision population enters C_b of g_W
-            const Real o = Real(2) * w5<Real>(DW) * ld<NT>(nu + DW * P + id);
+            const Real ow = Real(2) * w5<Real>(DW) * nu.load(oW);
 #pragma unroll
-            for (int i = 0; i < 5; ++i) lam[s][i] += o;
+            for (int i = 0; i < 5; ++i) lam[s][i] += ow;
         }
     }
     Real rsrc[S];
@@ -117,7 +118,8 @@ __global__ __launch_bounds__(1024) void k_adjoint_step(AdjArgs<Real> a)
         }
     }
     // (R Col)^T: nu_j = (1 - omega) lam_j + omega sum_i e_i lam_i + rsrc
-    const Real u = a.ua[id], v = a.ua[P + id];
+    const PopBlock<Real, false, WIDE> vel(a.ua, 2 * PB);
+    const Real u = vel.load(o), v = vel.load(o + PB);
     const Real uu = Real(1.5) * (u * u + v * v);
     Real e[5];
     e[0] = w5<Real>(0) * (Real(1) - uu);
@@ -131,8 +133,9 @@ __global__ __launch_bounds__(1024) void k_adjoint_step(AdjArgs<Real> a)
         const Real M = e[0] * lam[s][0] + e[1] * lam[s][1] + e[2] * lam[s][2] + e[3] * lam[s][3] +
                        e[4] * lam[s][4];
         const Real add = a.omega * M + rsrc[s];
+        const PopBlock<Real, NT, WIDE> out(a.nu_dst + (size_t)s * 5 * P, 5 * PB);
 #pragma unroll
-        for (int i = 0; i < 5; ++i) st<NT>(a.nu_dst + (s * 5 + i) * P + id, keep * lam[s][i] + add);
+        for (int i = 0; i < 5; ++i) out.store(o + i * PB, keep * lam[s][i] + add);
     }
 }
 
@@ -242,17 +245,16 @@ template <typename Real>
 void adjoint_launch(Ctx *c, const AdjArgs<Real> &a, hipStream_t s)
 {
     const dim3 g = c->L.grid(), b = c->L.block();
-    const bool nt = c->L.nontemporal;
-    if (c->p.nspecies == 2) {
-        if (nt)
-            hipLaunchKernelGGL((k_adjoint_step<Real, 2, true>), g, b, 0, s, a);
-        else
-            hipLaunchKernelGGL((k_adjoint_step<Real, 2, false>), g, b, 0, s, a);
-    } else {
-        if (nt)
-            hipLaunchKernelGGL((k_adjoint_step<Real, 3, true>), g, b, 0, s, a);
-        else
-            hipLaunchKernelGGL((k_adjoint_step<Real, 3, false>), g, b, 0, s, a);
+    const int sel = (c->L.nontemporal ? 1 : 0) | (c->L.wide ? 2 : 0) | (c->p.nspecies == 3 ? 4 : 0);
+    switch (sel) {
+    case 0: hipLaunchKernelGGL((k_adjoint_step<Real, 2, false, false>), g, b, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_adjoint_step<Real, 2, true, false>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_adjoint_step<Real, 2, false, true>), g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_adjoint_step<Real, 2, true, true>), g, b, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_adjoint_step<Real, 3, false, false>), g, b, 0, s, a); break;
+    case 5: hipLaunchKernelGGL((k_adjoint_step<Real, 3, true, false>), g, b, 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_adjoint_step<Real, 3, false, true>), g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_adjoint_step<Real, 3, true, true>), g, b, 0, s, a); break;
     }
 }
 

@@ -339,7 +339,7 @@ void batch_launch(lbf_batch b, int kind, int parity, bool write_u, hipStream_t s
 {
     const int4 *tiles = (const int4 *)(b->ws + b->off_tiles);
     const int *nt = (const int *)(b->ws + b->off_ntiles);
-    const dim3 g(b->grid), blk(b->tx * b->ty);
+    const dim3 blk(b->tx * b->ty);
     auto I = (const Inst<Real> *)(b->ws + b->off_inst);
     if (kind == KIND_ADR) {
         const dim3 ga(b->persistent ? b->grid : b->max_tiles);
