@@ -412,7 +412,7 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-            "kernel": "k_adr_step2<float,double,3,true,false>", "steps_per_launch": 2,
+            "kernel": "k_adr_step2<float,double,3,true,false,false>", "steps_per_launch": 2,
             "bytes_per_launch": step_bytes, "bytes_per_fluid_node": per_fluid,
             "avg_launch_us": round(launch_s * 1e6, 3),
             "us_per_step": round(kernel_ms * 1e3 / args.steps, 3),
