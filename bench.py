@@ -174,8 +174,9 @@ def batch_leg(steps=2000, flow_steps=2000):
     s = sweep_serial(ws, flow_steps, steps, check_every=1000)
     same = bool((b["product_flux"] == s["product_flux"]).all())
     return {"instances": len(ws), "nodes": nodes, "steps": steps,
-            "autotuned": {"tile": list(tile), "mode": "one block per tile" if flags & 8 else
-                          "persistent tile walk",
+            "autotuned": {"tile": list(tile), "mode": ("one block per tile" if flags & 8 else
+                                                    "persistent tile walk") +
+                          ("" if flags & 256 else ", two ADR steps per launch"),
                           "us_per_step": {str(k): round(v, 2) for k, v in timings.items()}},
             "batched_adr_s": round(b["adr_seconds"], 4), "serial_adr_s": round(s["adr_seconds"], 4),
             "batched_mlups": round(nodes * steps / b["adr_seconds"] / 1e6, 1),

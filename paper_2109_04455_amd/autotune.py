@@ -10,10 +10,14 @@ import os
 import torch
 
 DEFAULT_CANDIDATES = (
-    # (variant, tile_x, tile_y, flags)
-    (1, 256, 1, 0), (1, 512, 1, 0), (1, 128, 2, 0), (1, 64, 4, 0), (1, 1024, 1, 0),
-    (2, 64, 4, 0), (2, 64, 1, 0), (2, 128, 2, 0),
-    (1, 256, 1, 2),
+    # (variant, tile_x, tile_y, flags).  flags 0: two steps per launch with
+    # the intermediate state in LDS (its tile is fixed; variant and tile
+    # shape then apply to the single steps that end each block); flags bit 8
+    # (256): one step per launch; bit 1 (2): cached instead of streaming.
+    (1, 256, 1, 0), (1, 256, 1, 2),
+    (1, 256, 1, 256), (1, 512, 1, 256), (1, 128, 2, 256), (1, 64, 4, 256), (1, 1024, 1, 256),
+    (2, 64, 4, 256), (2, 64, 1, 256), (2, 128, 2, 256),
+    (1, 256, 1, 256 | 2),
 )
 
 
@@ -73,9 +77,10 @@ def autotune(node_type, k, *, real="f32", nspecies=3, tau_g=0.8, vel_scale=1.0, 
 
 
 BATCH_CANDIDATES = (
-    # (tile_x, tile_y, flags): flags bit 3 = one block per tile
+    # (tile_x, tile_y, flags): flags bit 3 = one block per tile (one-step
+    # kernels and the flow); bit 8 = one ADR step per launch instead of two
     (256, 1, 0), (256, 1, 8), (128, 2, 0), (128, 2, 8), (64, 4, 0), (64, 4, 8), (64, 1, 8),
-    (128, 1, 8),
+    (128, 1, 8), (128, 1, 8 | 256), (256, 1, 256),
 )
 
 
