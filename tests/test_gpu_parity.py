@@ -125,11 +125,27 @@ def test_tiny_cascade_parity_converged(real, tol):
 
 
 # --------------------------------------------- scaled and full-size FP32
-def test_c1_quarter_fp32_parity():
+@pytest.fixture(scope="module")
+def c1q_oracle():
     w = make_workload("C1q")
-    o = _oracle(w, 2000, 3000)
+    return w, _oracle(w, 2000, 3000)
+
+
+def test_c1_quarter_fp32_parity(c1q_oracle):
+    w, o = c1q_oracle
     g = _gpu_run(w, 2000, 3000)
     _compare(g, o, w, 1e-4, 1e-4, 1e-5)
+
+
+@pytest.mark.parametrize("flags", [16, 32, 4, 16 | 32])
+def test_c1_quarter_fp32_precision_options(c1q_oracle, flags):
+    # FP32 storage with FP32 node arithmetic (bit 4), FP32 arithmetic in the
+    # flow step only (bit 5), species A stored unshifted (bit 2): each stays
+    # within the FP32 bar of the FP64 oracle.  (Bits 2 and 4 together do
+    # not: 1.8e-4 on the A field, the loss the shifted storage avoids.)
+    w, o = c1q_oracle
+    g = _gpu_run(w, 2000, 3000, flags=flags)
+    _compare(g, o, w, 1e-4, 1e-4, 1e-4)
 
 
 def test_c2_quarter_fp32_parity_ragged_tiles():
