@@ -258,12 +258,14 @@ def test_vectorised_kernel_equals_one_node_per_thread(name, real):
     assert abs(out[0][-1] - out[1][-1]) <= 1e-6 * abs(out[1][-1]) + 1e-300
 
 
-@pytest.mark.parametrize("flags", [0, 2])
+@pytest.mark.parametrize("flags", [64, 1, 64 | 256])
 def test_streaming_and_cached_accesses_agree(flags):
-    # the cache policy of the population accesses changes no arithmetic
+    # the cache policy of the population accesses (bit 6 forces streaming on
+    # this cache-resident lattice, bit 1 forces cached) and the block order
+    # (bit 0: no XCD-aware order) change no arithmetic
     w = make_workload("C1q")
     out = []
-    for f in (flags, 2 - flags):
+    for f in (flags, 2 | (flags & 256)):
         c = _ctx(w, "f32", flags=f)
         c.flow_init()
         c.flow_run(200)
