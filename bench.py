@@ -380,10 +380,12 @@ def main():
     blocks = args.steps // 1000
     pairs = (1000 - 1) // 2
     pair_ms = (kernel_ms / blocks - (1000 - 2 * pairs) * single_ms) / pairs
-    # one two-step launch reads and writes the lattice once: its algorithmic
-    # bytes equal those of a single step
+    # algorithmic bytes of a launch: 129 B per fluid node-step (the ADR
+    # step's figure) times the two node-steps per node a launch performs;
+    # the lattice itself crosses HBM once per launch (`traffic`, measured)
     launch_s = pair_ms * 1e-3
-    achieved = step_bytes / launch_s / 1e9
+    launch_bytes = 2 * step_bytes
+    achieved = launch_bytes / launch_s / 1e9
     traffic = traffic_from_profiles(args.workload)
 
     # practical ceiling: a plain device copy of the same library
@@ -414,9 +416,11 @@ def main():
             "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
             "kernel": "k_adr_step2<float,double,3,true,false,false>", "steps_per_launch": 2,
-            "bytes_per_launch": step_bytes, "bytes_per_fluid_node": per_fluid,
+            "bytes_per_launch": launch_bytes, "bytes_per_fluid_node_step": per_fluid,
             "avg_launch_us": round(launch_s * 1e6, 3),
             "us_per_step": round(kernel_ms * 1e3 / args.steps, 3),
+            "measured_hbm_gbs": round(traffic / launch_s / 1e9, 1) if traffic else None,
+            "measured_hbm_frac": round(traffic / launch_s / 1e9 / PEAK_HBM_GBS, 4) if traffic else None,
             "single_step_kernel": {
                 "kernel": "k_adr_step<float,double,3,false,true,false>",
                 "avg_launch_us": round(single_ms * 1e3, 3),
