@@ -70,19 +70,20 @@ __device__ void interp2(const Field &f, double px, double py, double &uo, double
     const double fx = px - x0, fy = py - y0;
     double a[2][2], b[2][2];
     bool sol[2][2];
+    // the velocities are read at clamped (in-range) cells together with the
+    // cell types, so no load waits for a type; solid corners then take 0
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             const int cx = x0 + i, cy = y0 + j;
+            const int xc = cx < 0 ? 0 : (cx >= f.nx ? f.nx - 1 : cx);
+            const int yc = cy < 0 ? 0 : (cy >= f.ny ? f.ny - 1 : cy);
+            const size_t id = (size_t)yc * f.nx + xc;
+            const double ua = f.ux[id], vb = f.uy[id];
             sol[j][i] = solid(f, cx, cy);
-            a[j][i] = b[j][i] = 0.0;
-            if (!sol[j][i]) {
-                const int xc = cx < 0 ? 0 : (cx >= f.nx ? f.nx - 1 : cx);
-                const size_t id = (size_t)cy * f.nx + xc;
-                a[j][i] = f.ux[id];
-                b[j][i] = f.uy[id];
-            }
+            a[j][i] = sol[j][i] ? 0.0 : ua;
+            b[j][i] = sol[j][i] ? 0.0 : vb;
         }
     if (f.wall_mode == 1) {
         double wa[2][2], wb[2][2];
