@@ -70,8 +70,8 @@ __device__ void interp2(const Field &f, double px, double py, double &uo, double
     const double fx = px - x0, fy = py - y0;
     double a[2][2], b[2][2];
     bool sol[2][2];
-    // the velocities are read at clamped (in-range) cells together with the
-    // cell types, so no load waits for a type; solid corners then take 0
+    // the velocities and cell types are read at clamped (in-range) cells, all
+    // together, so no load waits for another; solid corners then take 0
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -81,7 +81,9 @@ __device__ void interp2(const Field &f, double px, double py, double &uo, double
             const int yc = cy < 0 ? 0 : (cy >= f.ny ? f.ny - 1 : cy);
             const size_t id = (size_t)yc * f.nx + xc;
             const double ua = f.ux[id], vb = f.uy[id];
-            sol[j][i] = solid(f, cx, cy);
+            const int tc = f.type[id];
+            // solid(): rows outside the lattice are solid, columns outside fluid
+            sol[j][i] = (cy < 0 || cy >= f.ny) ? true : ((cx < 0 || cx >= f.nx) ? false : tc != 0);
             a[j][i] = sol[j][i] ? 0.0 : ua;
             b[j][i] = sol[j][i] ? 0.0 : vb;
         }
@@ -117,11 +119,13 @@ __device__ void interp2(const Field &f, double px, double py, double &uo, double
 
 // Specular reflection of the move (px, py) -> (qx, qy) at the faces of solid
 // cells; a move that would still end in a solid cell is cancelled.
-__device__ void reflect(const Field &f, double px, double py, double &qx, double &qy)
+// `lands_solid`: solid(f, cell_of(qx), cell_of(qy)), known to the caller.
+__device__ void reflect(const Field &f, double px, double py, double &qx, double &qy,
+                        bool lands_solid)
 {
     const int ox = cell_of(px), oy = cell_of(py);
     const int nxc = cell_of(qx), nyc = cell_of(qy);
-    if (!solid(f, nxc, nyc)) return;
+    if (!lands_solid) return;
     bool done = false;
     if (nxc != ox && solid(f, nxc, oy)) {
         qx = 2.0 * (nxc > ox ? ox + 0.5 : ox - 0.5) - qx;
@@ -141,6 +145,30 @@ __device__ void reflect(const Field &f, double px, double py, double &qx, double
     }
 }
 
+// Cell types of a cell and of its four neighbours (+x, +y, -x, -y), read
+// together at clamped (in-range) indices so that none waits for another; the
+// caller ignores the ones outside the lattice.
+struct TypesAround {
+    int c;     // the cell itself
+    int n[4];  // its neighbours
+};
+
+__device__ __forceinline__ TypesAround types_around(const Field &f, int cx, int cy)
+{
+    auto at = [&](int x, int y) {
+        x = x < 0 ? 0 : (x >= f.nx ? f.nx - 1 : x);
+        y = y < 0 ? 0 : (y >= f.ny ? f.ny - 1 : y);
+        return (int)f.type[(size_t)y * f.nx + x];
+    };
+    TypesAround t;
+    t.c = at(cx, cy);
+    t.n[0] = at(cx + 1, cy);
+    t.n[1] = at(cx, cy + 1);
+    t.n[2] = at(cx - 1, cy);
+    t.n[3] = at(cx, cy - 1);
+    return t;
+}
+
 // One step of one particle; returns the signed crossing of x = plane.
 __device__ int move(const Field &f, uint64_t id, uint64_t t, double buf_hi, double plane,
                     double &x, double &y, uint8_t &s)
@@ -154,18 +182,26 @@ __device__ int move(const Field &f, uint64_t id, uint64_t t, double buf_hi, doub
     sincos(2.0 * M_PI * draw(f.seed, id, t, 0), &sn, &cs);
     double x1 = x0 + u * f.dt + f.len * cs;
     double y1 = y0 + v * f.dt + f.len * sn;
-    reflect(f, x0, y0, x1, y1);
+    // the types around the landing cell, which is almost always the final one
+    int cx = cell_of(x1), cy = cell_of(y1);
+    TypesAround ty = types_around(f, cx, cy);
+    const bool lands_solid = (cy < 0 || cy >= f.ny) ? true : ((cx < 0 || cx >= f.nx) ? false : ty.c != 0);
+    reflect(f, x0, y0, x1, y1, lands_solid);
     if (x1 < buf_hi && x0 >= buf_hi && s != 0) x1 = 2.0 * buf_hi - x1;  // B, C at the inlet
     const int ds = (x0 < plane && x1 >= plane) ? 1 : ((x0 >= plane && x1 < plane) ? -1 : 0);
-    const int cx = cell_of(x1), cy = cell_of(y1);
-    if (cx >= 0 && cx < f.nx && cy >= 0 && cy < f.ny && f.type[(size_t)cy * f.nx + cx] == 0) {
+    if (cell_of(x1) != cx || cell_of(y1) != cy) {
+        cx = cell_of(x1);
+        cy = cell_of(y1);
+        ty = types_around(f, cx, cy);
+    }
+    if (cx >= 0 && cx < f.nx && cy >= 0 && cy < f.ny && ty.c == 0) {
         const int DX[4] = {1, 0, -1, 0}, DY[4] = {0, 1, 0, -1};
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
             const int sx = cx + DX[d], sy = cy + DY[d];
             if (sx < 0 || sx >= f.nx || sy < 0 || sy >= f.ny) continue;
-            const int ty = f.type[(size_t)sy * f.nx + sx];
-            const int src = ty == 2 ? 0 : (ty == 3 && f.ns == 3 ? 1 : -1);
+            const int tn = ty.n[d];
+            const int src = tn == 2 ? 0 : (tn == 3 && f.ns == 3 ? 1 : -1);
             if (src != s) continue;
             const double dist = d == 0 ? cx + 0.5 - x1 : d == 1 ? cy + 0.5 - y1
                               : d == 2 ? x1 - (cx - 0.5) : y1 - (cy - 0.5);
