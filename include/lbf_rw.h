@@ -53,7 +53,9 @@ typedef struct {
     double density;      /* particles of A per unit area, (0, 200]               */
     double vel_scale;    /* velocity = vel_scale * field, >= 0                   */
     uint64_t seed;
-    long capacity;       /* maximum number of particles held                     */
+    long capacity;       /* maximum number of particles held (the particles that
+                            left stay in the arrays until the next compaction,
+                            at most 16 steps' worth)                            */
 } lbf_rw_params;
 
 lbf_status lbf_rw_params_default(lbf_rw_params *p, int nx, int ny);
@@ -71,7 +73,9 @@ lbf_status lbf_rw_fill(lbf_rw rw);
  * Asynchronous; LBF_ENOMEM from lbf_rw_counts if the capacity was hit. */
 lbf_status lbf_rw_run(lbf_rw rw, long nsteps, int measure);
 /* N[0..nspecies) = net crossings per unit time over the measured steps,
- * *nparticles, *steps (all may be NULL).  Synchronises. */
+ * *nparticles = the particles the last step moved (those inside the domain
+ * at its start plus the reservoir refill), *steps (all may be NULL).
+ * Synchronises. */
 lbf_status lbf_rw_counts(lbf_rw rw, double *N, long *nparticles, long *steps);
 /* Trajectory mode: advance np caller-owned particles (device arrays ids u64,
  * x, y double, species u8, updated in place) through steps t0 .. t0+steps-1

@@ -1,7 +1,8 @@
 // GPU random-walk particle tracker (include/lbf_rw.h): one thread per
-// particle, particles held as structure-of-arrays, the reservoir refilled and
-// the exited particles dropped by an order-preserving stream compaction every
-// step, crossing counts in 64-bit integer atomics.  A step is a fixed chain of
+// particle, particles held as structure-of-arrays, the reservoir refilled
+// every step and the particles that left dropped by an order-preserving
+// stream compaction every few steps (skipped by the move in between),
+// crossing counts in 64-bit integer atomics.  A step is a fixed chain of
 // kernels whose sizes live on the device, so blocks of steps are captured as
 // HIP graphs.
 #include <hip/hip_runtime.h>
@@ -23,6 +24,9 @@ constexpr uint64_t ID_INSERT = 1ULL << 62;
 constexpr uint64_t ID_COUNT = 1ULL << 63;
 constexpr int SCAN_BLOCKS = 1024;  // blocks of every scan pass (fixed: sizes are on the device)
 constexpr int SCAN_THREADS = 256;
+// the arrays are compacted every COMPACT_EVERY steps of a graph block; in
+// between, particles that left stay in place (skipped by the move)
+constexpr long COMPACT_EVERY = 16;
 constexpr double BUF_LO = -1.5, BUF_HI = -0.5;  // reservoir strip
 
 __device__ __forceinline__ uint64_t mix(uint64_t z)
@@ -230,6 +234,7 @@ struct Scalars {
     long long n_alive;   // survivors of the last compaction
     long long t;         // step counter
     long long cross[3];  // signed crossings while measuring
+    long long n_held;    // particles moved by the last step
     int overflow;        // capacity was hit
 };
 
@@ -364,37 +369,50 @@ __global__ void k_set_count(Scalars *sc, long long buf_count, long long capacity
 {
     const long long n = sc->n_alive + buf_count;
     sc->n_cur = n < capacity ? n : capacity;
+    sc->n_held = 0;
 }
 
+// A step without compaction appends its new particles after every particle
+// of the arrays, the ones that left since the last compaction included.
+__global__ void k_lazy_base(Scalars *sc) { sc->n_alive = sc->n_cur; }
+
 // move every particle; crossing counts reduced per block, then one atomic
-// per block and species
+// per block and species.  Particles below this step's insertion point
+// (n_alive) that are no longer alive left the domain since the last
+// compaction and stay where they are until the next one removes them; the
+// particles moved are counted (n_held).
 __global__ __launch_bounds__(256) void k_move(Field f, Parts p, Scalars *sc, double plane,
                                               int measure)
 {
-    __shared__ long long cnt[3];
-    if (threadIdx.x < 3) cnt[threadIdx.x] = 0;
+    __shared__ long long cnt[4];
+    if (threadIdx.x < 4) cnt[threadIdx.x] = 0;
     __syncthreads();
-    const long long n = sc->n_cur;
+    const long long n = sc->n_cur, first_new = sc->n_alive;
     const uint64_t t = (uint64_t)sc->t;
     int c[3] = {0, 0, 0};
+    int moved = 0;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
         double x = p.x[i], y = p.y[i];
+        if (i < first_new && !alive(x, f.nx)) continue;
         uint8_t s = p.sp[i];
         const uint8_t s0 = s;
         const int ds = move(f, p.id[i], t, BUF_HI, plane, x, y, s);
         c[s0] += ds;
+        ++moved;
         p.x[i] = x;
         p.y[i] = y;
         p.sp[i] = s;
     }
-    if (measure) {
+    if (moved) atomicAdd((unsigned long long *)&cnt[3], (unsigned long long)moved);
+    if (measure)
         for (int s = 0; s < 3; ++s)
             if (c[s]) atomicAdd((unsigned long long *)&cnt[s], (unsigned long long)(long long)c[s]);
-        __syncthreads();
-        if (threadIdx.x < 3 && cnt[threadIdx.x])
-            atomicAdd((unsigned long long *)&sc->cross[threadIdx.x], (unsigned long long)cnt[threadIdx.x]);
-    }
+    __syncthreads();
+    if (measure && threadIdx.x < 3 && cnt[threadIdx.x])
+        atomicAdd((unsigned long long *)&sc->cross[threadIdx.x], (unsigned long long)cnt[threadIdx.x]);
+    if (threadIdx.x == 3 && cnt[3])
+        atomicAdd((unsigned long long *)&sc->n_held, (unsigned long long)cnt[3]);
 }
 
 __global__ void k_tick(Scalars *sc) { sc->t += 1; }
@@ -473,6 +491,7 @@ __global__ void k_fill_finish(Scalars *sc, const long long *total, long long cap
     sc->n_alive = 0;
     sc->t = 0;
     sc->cross[0] = sc->cross[1] = sc->cross[2] = 0;
+    sc->n_held = sc->n_cur;
 }
 
 __global__ void k_walk(Field f, long long np, const uint64_t *ids, double *x, double *y,
@@ -581,15 +600,23 @@ Parts parts(Rw *r, int b)
                  (uint8_t *)r->ptr(r->off.sp[b]), (uint64_t *)r->ptr(r->off.id[b])};
 }
 
-hipError_t enqueue_step(Rw *r, int par, int measure, hipStream_t s)
+// One step from the arrays of parity `par`.  With `compact` the survivors are
+// first compacted into the other arrays (order preserved) and the step works
+// there; without, it appends to and moves the arrays it found.  Particles do
+// not interact, so where the compactions fall changes no result.
+hipError_t enqueue_step(Rw *r, int par, int measure, bool compact, hipStream_t s)
 {
     Scalars *sc = (Scalars *)r->ptr(r->off.sc);
     long long *bsum = (long long *)r->ptr(r->off.bsum), *boff = (long long *)r->ptr(r->off.boff);
-    const Parts src = parts(r, par), dst = parts(r, par ^ 1);
+    const Parts src = parts(r, par), dst = parts(r, compact ? par ^ 1 : par);
     const long long C = r->p.capacity;
-    hipLaunchKernelGGL(k_count_alive, dim3(SCAN_BLOCKS), dim3(SCAN_THREADS), 0, s, src, sc, r->p.nx, bsum);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_BLOCKS), 0, s, bsum, boff, &sc->n_alive);
-    hipLaunchKernelGGL(k_compact, dim3(SCAN_BLOCKS), dim3(SCAN_THREADS), 0, s, src, dst, sc, r->p.nx, boff);
+    if (compact) {
+        hipLaunchKernelGGL(k_count_alive, dim3(SCAN_BLOCKS), dim3(SCAN_THREADS), 0, s, src, sc, r->p.nx, bsum);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_BLOCKS), 0, s, bsum, boff, &sc->n_alive);
+        hipLaunchKernelGGL(k_compact, dim3(SCAN_BLOCKS), dim3(SCAN_THREADS), 0, s, src, dst, sc, r->p.nx, boff);
+    } else {
+        hipLaunchKernelGGL(k_lazy_base, dim3(1), dim3(1), 0, s, sc);
+    }
     hipLaunchKernelGGL(k_insert, dim3(64), dim3(256), 0, s, dst, sc, r->buf_count, C, r->p.seed,
                        0.5, r->p.ny - 1.5);
     hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, s, sc, r->buf_count, C);
@@ -611,8 +638,9 @@ lbf_status run_block(Rw *r, long n, int measure)
         int p = r->par;
         hipError_t le = hipSuccess;
         for (long i = 0; i < n && le == hipSuccess; ++i) {
-            le = enqueue_step(r, p, measure, r->cap_stream);
-            p ^= 1;
+            const bool compact = i % COMPACT_EVERY == 0;
+            le = enqueue_step(r, p, measure, compact, r->cap_stream);
+            if (compact) p ^= 1;
         }
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(r->cap_stream, &g);
@@ -629,7 +657,7 @@ lbf_status run_block(Rw *r, long n, int measure)
     }
     hipError_t e = hipGraphLaunch(it->second, r->stream);
     if (e != hipSuccess) return hip_fail(r, e, "hipGraphLaunch");
-    if (n & 1) r->par ^= 1;
+    if (((n + COMPACT_EVERY - 1) / COMPACT_EVERY) & 1) r->par ^= 1;  // one swap per compaction
     return LBF_OK;
 }
 
@@ -809,7 +837,7 @@ lbf_status lbf_rw_counts(lbf_rw r, double *N, long *np, long *steps)
     if (N)
         for (int s = 0; s < r->p.nspecies; ++s)
             N[s] = r->measured ? (double)h.cross[s] / (r->measured * r->p.dt) : 0.0;
-    if (np) *np = (long)h.n_cur;
+    if (np) *np = (long)h.n_held;
     if (steps) *steps = r->measured;
     return LBF_OK;
 }
