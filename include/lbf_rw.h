@@ -62,8 +62,11 @@ lbf_status lbf_rw_params_default(lbf_rw_params *p, int nx, int ny);
 lbf_status lbf_rw_create(const lbf_rw_params *p, lbf_rw *out);
 lbf_status lbf_rw_workspace_bytes(lbf_rw rw, size_t *bytes);
 lbf_status lbf_rw_bind(lbf_rw rw, void *workspace_dev, size_t bytes, void *hip_stream);
-/* Geometry and fields (device arrays [ny][nx], copied): node_type u8, flow
- * velocity ux, uy and rates k as double.  Rows 0 and ny-1 must be solid. */
+/* Geometry and fields (device arrays [ny][nx], copied): node_type u8 with
+ * values 0..3, flow velocity ux, uy and rates k as double.  Rows 0 and ny-1
+ * must be solid (LBF_EINVAL otherwise).  The copy interleaves ux and uy and
+ * keeps per cell the types of the 3 x 3 cells around it, so a particle step
+ * reads each corner velocity and a whole neighbourhood of types in one load. */
 lbf_status lbf_rw_set_fields(lbf_rw rw, const uint8_t *node_type_dev, const double *ux_dev,
                              const double *uy_dev, const double *k_dev);
 /* Uniform A at `density` in every fluid cell; resets the step and the

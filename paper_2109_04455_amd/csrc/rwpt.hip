@@ -48,7 +48,9 @@ __device__ __forceinline__ double draw(uint64_t seed, uint64_t id, uint64_t t, u
 struct Field {
     int nx, ny, ns, wall_mode;
     const uint8_t *type;
-    const double *ux, *uy, *k;
+    const double2 *uv;   // (ux, uy) of each cell, one 16-byte load
+    const uint32_t *nb;  // types of the 3 x 3 cells around each cell, 2 bits each
+    const double *k;
     double vs;      // velocity scale
     double dt, len, zone, rate_w;
     uint64_t seed;
@@ -63,6 +65,16 @@ __device__ __forceinline__ bool solid(const Field &f, int cx, int cy)
 
 __device__ __forceinline__ int cell_of(double p) { return (int)floor(p + 0.5); }
 
+__device__ __forceinline__ int clampi(int v, int hi) { return v < 0 ? 0 : (v > hi ? hi : v); }
+
+// Type of cell (x + dx, y + dy), dx, dy in {-1, 0, 1}, from the word of
+// cell (x, y).  Neighbours outside the lattice hold what solid() reports
+// there (rows outside solid, columns outside fluid).
+__device__ __forceinline__ int nb_type(uint32_t w, int dx, int dy)
+{
+    return (int)(w >> (2 * (3 * (dy + 1) + dx + 1))) & 3;
+}
+
 // Bilinear interpolation of the two velocity components at (px, py); in
 // wall_mode 1 a solid corner takes minus the mean of its fluid neighbours
 // along the cell edges (or minus the diagonal fluid corner), so the
@@ -74,18 +86,21 @@ __device__ void interp2(const Field &f, double px, double py, double &uo, double
     const double fx = px - x0, fy = py - y0;
     double a[2][2], b[2][2];
     bool sol[2][2];
-    // the velocities and cell types are read at clamped (in-range) cells, all
-    // together, so no load waits for another; solid corners then take 0
+    // the velocities are read at clamped (in-range) cells, all together, and
+    // the corner types come from the type word of the clamped lower-left
+    // corner (every in-range corner lies at offset 0 or +1 from it); solid
+    // corners then take 0
+    const int xl = clampi(x0, f.nx - 1), yl = clampi(y0, f.ny - 1);
+    const uint32_t w = f.nb[(size_t)yl * f.nx + xl];
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             const int cx = x0 + i, cy = y0 + j;
-            const int xc = cx < 0 ? 0 : (cx >= f.nx ? f.nx - 1 : cx);
-            const int yc = cy < 0 ? 0 : (cy >= f.ny ? f.ny - 1 : cy);
-            const size_t id = (size_t)yc * f.nx + xc;
-            const double ua = f.ux[id], vb = f.uy[id];
-            const int tc = f.type[id];
+            const int xc = clampi(cx, f.nx - 1), yc = clampi(cy, f.ny - 1);
+            const double2 q = f.uv[(size_t)yc * f.nx + xc];
+            const double ua = q.x, vb = q.y;
+            const int tc = nb_type(w, xc - xl, yc - yl);
             // solid(): rows outside the lattice are solid, columns outside fluid
             sol[j][i] = (cy < 0 || cy >= f.ny) ? true : ((cx < 0 || cx >= f.nx) ? false : tc != 0);
             a[j][i] = sol[j][i] ? 0.0 : ua;
@@ -149,9 +164,9 @@ __device__ void reflect(const Field &f, double px, double py, double &qx, double
     }
 }
 
-// Cell types of a cell and of its four neighbours (+x, +y, -x, -y), read
-// together at clamped (in-range) indices so that none waits for another; the
-// caller ignores the ones outside the lattice.
+// Cell types of a cell and of its four neighbours (+x, +y, -x, -y), from one
+// type word (of the clamped cell); the caller ignores the cell outside the
+// lattice and the neighbours outside it.
 struct TypesAround {
     int c;     // the cell itself
     int n[4];  // its neighbours
@@ -159,17 +174,13 @@ struct TypesAround {
 
 __device__ __forceinline__ TypesAround types_around(const Field &f, int cx, int cy)
 {
-    auto at = [&](int x, int y) {
-        x = x < 0 ? 0 : (x >= f.nx ? f.nx - 1 : x);
-        y = y < 0 ? 0 : (y >= f.ny ? f.ny - 1 : y);
-        return (int)f.type[(size_t)y * f.nx + x];
-    };
+    const uint32_t w = f.nb[(size_t)clampi(cy, f.ny - 1) * f.nx + clampi(cx, f.nx - 1)];
     TypesAround t;
-    t.c = at(cx, cy);
-    t.n[0] = at(cx + 1, cy);
-    t.n[1] = at(cx, cy + 1);
-    t.n[2] = at(cx - 1, cy);
-    t.n[3] = at(cx, cy - 1);
+    t.c = nb_type(w, 0, 0);
+    t.n[0] = nb_type(w, 1, 0);
+    t.n[1] = nb_type(w, 0, 1);
+    t.n[2] = nb_type(w, -1, 0);
+    t.n[3] = nb_type(w, 0, -1);
     return t;
 }
 
@@ -417,6 +428,29 @@ __global__ __launch_bounds__(256) void k_move(Field f, Parts p, Scalars *sc, dou
 
 __global__ void k_tick(Scalars *sc) { sc->t += 1; }
 
+// Per cell: the velocity pair, and the types of the 3 x 3 cells around it
+// (bits 2 (3 (dy + 1) + dx + 1)), with solid()'s convention outside.
+__global__ void k_pack_fields(Field f, const double *ux, const double *uy, double2 *uv, uint32_t *nb)
+{
+    const long long n = (long long)f.nx * f.ny;
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+         c += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(c % f.nx), y = (int)(c / f.nx);
+        uv[c] = make_double2(ux[c], uy[c]);
+        uint32_t w = 0;
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int sx = x + dx, sy = y + dy;
+                uint32_t t;
+                if (sy < 0 || sy >= f.ny) t = 1;
+                else if (sx < 0 || sx >= f.nx) t = 0;
+                else t = f.type[(size_t)sy * f.nx + sx];
+                w |= t << (2 * (3 * (dy + 1) + dx + 1));
+            }
+        nb[c] = w;
+    }
+}
+
 // ---- initial fill ------------------------------------------------------------
 __global__ void k_fill_count(Field f, double density, int *counts)
 {
@@ -516,7 +550,7 @@ struct lbf_rw_s {
     bool valid = false;
     std::string err;
     struct Offsets {
-        size_t type, ux, uy, k, x[2], y[2], sp[2], id[2], counts, bsum, boff, total, sc;
+        size_t type, uv, nb, k, x[2], y[2], sp[2], id[2], counts, bsum, boff, total, sc;
     } off{};
     size_t ws_need = 0;
     char *ws = nullptr;
@@ -557,8 +591,8 @@ void layout(Rw *r)
         return o;
     };
     r->off.type = take(n);
-    r->off.ux = take(8 * n);
-    r->off.uy = take(8 * n);
+    r->off.uv = take(16 * n);
+    r->off.nb = take(4 * n);
     r->off.k = take(8 * n);
     for (int b = 0; b < 2; ++b) {
         r->off.x[b] = take(8 * C);
@@ -582,8 +616,8 @@ Field field(Rw *r)
     f.ns = r->p.nspecies;
     f.wall_mode = r->p.wall_mode;
     f.type = (const uint8_t *)r->ptr(r->off.type);
-    f.ux = (const double *)r->ptr(r->off.ux);
-    f.uy = (const double *)r->ptr(r->off.uy);
+    f.uv = (const double2 *)r->ptr(r->off.uv);
+    f.nb = (const uint32_t *)r->ptr(r->off.nb);
     f.k = (const double *)r->ptr(r->off.k);
     f.vs = r->p.vel_scale;
     f.dt = r->p.dt;
@@ -774,12 +808,17 @@ lbf_status lbf_rw_set_fields(lbf_rw r, const uint8_t *type, const double *ux, co
         if (t[x] == 0 || t[n - r->p.nx + x] == 0) return fail(r, LBF_EINVAL, "rows 0 and ny-1 must be solid");
     for (uint8_t v : t)
         if (v > 3) return fail(r, LBF_EINVAL, "node_type values must be 0..3");
-    const void *src[4] = {type, ux, uy, k};
-    const size_t off[4] = {r->off.type, r->off.ux, r->off.uy, r->off.k};
-    const size_t bytes[4] = {n, 8 * n, 8 * n, 8 * n};
-    for (int i = 0; i < 4 && e == hipSuccess; ++i)
+    const void *src[2] = {type, k};
+    const size_t off[2] = {r->off.type, r->off.k};
+    const size_t bytes[2] = {n, 8 * n};
+    for (int i = 0; i < 2 && e == hipSuccess; ++i)
         e = hipMemcpyAsync(r->ptr(off[i]), src[i], bytes[i], hipMemcpyDeviceToDevice, r->stream);
     if (e != hipSuccess) return hip_fail(r, e, "copy fields");
+    const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_pack_fields, dim3(blocks), dim3(256), 0, r->stream, field(r), ux, uy,
+                       (double2 *)r->ptr(r->off.uv), (uint32_t *)r->ptr(r->off.nb));
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(r, e, "pack fields");
     r->fields_set = true;
     r->filled = false;
     return LBF_OK;
