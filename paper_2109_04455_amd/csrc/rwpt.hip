@@ -49,62 +49,89 @@ struct Field {
     int nx, ny, ns, wall_mode;
     const uint8_t *type;
     const double2 *uv;   // (ux, uy) of each cell, one 16-byte load
-    const uint32_t *nb;  // types of the 3 x 3 cells around each cell, 2 bits each
+    const uint64_t *nb;  // [ny + 6][nx + 6] windows of types, of cells x, y in [-3, n + 3)
     const double *k;
     double vs;      // velocity scale
     double dt, len, zone, rate_w;
     uint64_t seed;
 };
 
-__device__ __forceinline__ bool solid(const Field &f, int cx, int cy)
-{
-    if (cy < 0 || cy >= f.ny) return true;
-    if (cx < 0 || cx >= f.nx) return false;
-    return f.type[(size_t)cy * f.nx + cx] != 0;
-}
-
 __device__ __forceinline__ int cell_of(double p) { return (int)floor(p + 0.5); }
 
 __device__ __forceinline__ int clampi(int v, int hi) { return v < 0 ? 0 : (v > hi ? hi : v); }
 
-// Type of cell (x + dx, y + dy), dx, dy in {-1, 0, 1}, from the word of
-// cell (x, y).  Neighbours outside the lattice hold what solid() reports
-// there (rows outside solid, columns outside fluid).
-__device__ __forceinline__ int nb_type(uint32_t w, int dx, int dy)
+// Type of cell (x, y) read from the lattice: rows outside are solid (1),
+// columns outside fluid (0).
+__device__ __forceinline__ int type_read(const Field &f, int x, int y)
 {
-    return (int)(w >> (2 * (3 * (dy + 1) + dx + 1))) & 3;
+    if (y < 0 || y >= f.ny) return 1;
+    if (x < 0 || x >= f.nx) return 0;
+    return f.type[(size_t)y * f.nx + x];
 }
+
+// The types of the 5 x 5 cells around a particle's cell (ox, oy), from one
+// 64-bit word (2 bits per cell, outside the lattice as type_read).  Words
+// exist for ox in [-3, nx + 3) and oy in [-3, ny + 3); beyond, every cell of
+// the window lies outside the lattice on that side, so the word of the
+// nearest stored cell is the same.  A step shorter than one cell per axis
+// lands within one cell of (ox, oy), so its interpolation corners, reflection
+// tests, landing cell and that cell's neighbours all lie in the window.
+struct Window {
+    uint64_t w;
+    int ox, oy;
+};
+
+__device__ __forceinline__ Window window_at(const Field &f, int ox, int oy)
+{
+    Window v;
+    v.ox = ox;
+    v.oy = oy;
+    const int wx = ox < -3 ? -3 : (ox > f.nx + 2 ? f.nx + 2 : ox);
+    const int wy = oy < -3 ? -3 : (oy > f.ny + 2 ? f.ny + 2 : oy);
+    v.w = f.nb[(size_t)(wy + 3) * (f.nx + 6) + (wx + 3)];
+    return v;
+}
+
+// cell (x, y) within two cells of (ox, oy) in each axis
+__device__ __forceinline__ int win_type(const Window &v, int x, int y)
+{
+    return (int)(v.w >> (2 * (5 * (y - v.oy + 2) + x - v.ox + 2))) & 3;
+}
+
+// Cell types for the rest of a step: from the window (steps shorter than a
+// cell per axis) or read from the lattice.
+struct WinTypes {
+    const Window &v;
+    __device__ __forceinline__ int operator()(int x, int y) const { return win_type(v, x, y); }
+};
+struct ReadTypes {
+    const Field &f;
+    __device__ __forceinline__ int operator()(int x, int y) const { return type_read(f, x, y); }
+};
 
 // Bilinear interpolation of the two velocity components at (px, py); in
 // wall_mode 1 a solid corner takes minus the mean of its fluid neighbours
 // along the cell edges (or minus the diagonal fluid corner), so the
 // interpolant is zero on the half-way wall.  Corner classification is shared
 // by both components.
-__device__ void interp2(const Field &f, double px, double py, double &uo, double &vo)
+__device__ void interp2(const Field &f, const Window &wv, double px, double py, double &uo,
+                        double &vo)
 {
     const int x0 = (int)floor(px), y0 = (int)floor(py);
     const double fx = px - x0, fy = py - y0;
     double a[2][2], b[2][2];
     bool sol[2][2];
-    // the velocities are read at clamped (in-range) cells, all together, and
-    // the corner types come from the type word of the clamped lower-left
-    // corner (every in-range corner lies at offset 0 or +1 from it); solid
-    // corners then take 0
-    const int xl = clampi(x0, f.nx - 1), yl = clampi(y0, f.ny - 1);
-    const uint32_t w = f.nb[(size_t)yl * f.nx + xl];
+    // the velocities are read at clamped (in-range) cells, all together;
+    // solid corners then take 0
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             const int cx = x0 + i, cy = y0 + j;
-            const int xc = clampi(cx, f.nx - 1), yc = clampi(cy, f.ny - 1);
-            const double2 q = f.uv[(size_t)yc * f.nx + xc];
-            const double ua = q.x, vb = q.y;
-            const int tc = nb_type(w, xc - xl, yc - yl);
-            // solid(): rows outside the lattice are solid, columns outside fluid
-            sol[j][i] = (cy < 0 || cy >= f.ny) ? true : ((cx < 0 || cx >= f.nx) ? false : tc != 0);
-            a[j][i] = sol[j][i] ? 0.0 : ua;
-            b[j][i] = sol[j][i] ? 0.0 : vb;
+            const double2 q = f.uv[(size_t)clampi(cy, f.ny - 1) * f.nx + clampi(cx, f.nx - 1)];
+            sol[j][i] = win_type(wv, cx, cy) != 0;
+            a[j][i] = sol[j][i] ? 0.0 : q.x;
+            b[j][i] = sol[j][i] ? 0.0 : q.y;
         }
     if (f.wall_mode == 1) {
         double wa[2][2], wb[2][2];
@@ -138,19 +165,19 @@ __device__ void interp2(const Field &f, double px, double py, double &uo, double
 
 // Specular reflection of the move (px, py) -> (qx, qy) at the faces of solid
 // cells; a move that would still end in a solid cell is cancelled.
-// `lands_solid`: solid(f, cell_of(qx), cell_of(qy)), known to the caller.
-__device__ void reflect(const Field &f, double px, double py, double &qx, double &qy,
-                        bool lands_solid)
+template <typename Types>
+__device__ __forceinline__ void reflect(const Types &type, double px, double py, double &qx,
+                                        double &qy)
 {
     const int ox = cell_of(px), oy = cell_of(py);
     const int nxc = cell_of(qx), nyc = cell_of(qy);
-    if (!lands_solid) return;
+    if (type(nxc, nyc) == 0) return;
     bool done = false;
-    if (nxc != ox && solid(f, nxc, oy)) {
+    if (nxc != ox && type(nxc, oy) != 0) {
         qx = 2.0 * (nxc > ox ? ox + 0.5 : ox - 0.5) - qx;
         done = true;
     }
-    if (nyc != oy && solid(f, ox, nyc)) {
+    if (nyc != oy && type(ox, nyc) != 0) {
         qy = 2.0 * (nyc > oy ? oy + 0.5 : oy - 0.5) - qy;
         done = true;
     }
@@ -158,64 +185,31 @@ __device__ void reflect(const Field &f, double px, double py, double &qx, double
         qx = 2.0 * (nxc > ox ? ox + 0.5 : ox - 0.5) - qx;
         qy = 2.0 * (nyc > oy ? oy + 0.5 : oy - 0.5) - qy;
     }
-    if (solid(f, cell_of(qx), cell_of(qy))) {
+    if (type(cell_of(qx), cell_of(qy)) != 0) {
         qx = px;
         qy = py;
     }
 }
 
-// Cell types of a cell and of its four neighbours (+x, +y, -x, -y), from one
-// type word (of the clamped cell); the caller ignores the cell outside the
-// lattice and the neighbours outside it.
-struct TypesAround {
-    int c;     // the cell itself
-    int n[4];  // its neighbours
-};
-
-__device__ __forceinline__ TypesAround types_around(const Field &f, int cx, int cy)
+// The rest of a step after the move to (x1, y1): reflection, the inlet rule
+// for B and C, the crossing of x = plane and the reaction; returns the
+// crossing.
+template <typename Types>
+__device__ __forceinline__ int finish(const Field &f, const Types &type, uint64_t id, uint64_t t,
+                                      double buf_hi, double plane, double x0, double y0,
+                                      double &x1, double &y1, uint8_t &s)
 {
-    const uint32_t w = f.nb[(size_t)clampi(cy, f.ny - 1) * f.nx + clampi(cx, f.nx - 1)];
-    TypesAround t;
-    t.c = nb_type(w, 0, 0);
-    t.n[0] = nb_type(w, 1, 0);
-    t.n[1] = nb_type(w, 0, 1);
-    t.n[2] = nb_type(w, -1, 0);
-    t.n[3] = nb_type(w, 0, -1);
-    return t;
-}
-
-// One step of one particle; returns the signed crossing of x = plane.
-__device__ int move(const Field &f, uint64_t id, uint64_t t, double buf_hi, double plane,
-                    double &x, double &y, uint8_t &s)
-{
-    const double x0 = x, y0 = y;
-    double u, v;
-    interp2(f, x0, y0, u, v);
-    u *= f.vs;
-    v *= f.vs;
-    double sn, cs;
-    sincos(2.0 * M_PI * draw(f.seed, id, t, 0), &sn, &cs);
-    double x1 = x0 + u * f.dt + f.len * cs;
-    double y1 = y0 + v * f.dt + f.len * sn;
-    // the types around the landing cell, which is almost always the final one
-    int cx = cell_of(x1), cy = cell_of(y1);
-    TypesAround ty = types_around(f, cx, cy);
-    const bool lands_solid = (cy < 0 || cy >= f.ny) ? true : ((cx < 0 || cx >= f.nx) ? false : ty.c != 0);
-    reflect(f, x0, y0, x1, y1, lands_solid);
+    reflect(type, x0, y0, x1, y1);
     if (x1 < buf_hi && x0 >= buf_hi && s != 0) x1 = 2.0 * buf_hi - x1;  // B, C at the inlet
     const int ds = (x0 < plane && x1 >= plane) ? 1 : ((x0 >= plane && x1 < plane) ? -1 : 0);
-    if (cell_of(x1) != cx || cell_of(y1) != cy) {
-        cx = cell_of(x1);
-        cy = cell_of(y1);
-        ty = types_around(f, cx, cy);
-    }
-    if (cx >= 0 && cx < f.nx && cy >= 0 && cy < f.ny && ty.c == 0) {
+    const int cx = cell_of(x1), cy = cell_of(y1);
+    if (cx >= 0 && cx < f.nx && cy >= 0 && cy < f.ny && type(cx, cy) == 0) {
         const int DX[4] = {1, 0, -1, 0}, DY[4] = {0, 1, 0, -1};
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
             const int sx = cx + DX[d], sy = cy + DY[d];
             if (sx < 0 || sx >= f.nx || sy < 0 || sy >= f.ny) continue;
-            const int tn = ty.n[d];
+            const int tn = type(sx, sy);
             const int src = tn == 2 ? 0 : (tn == 3 && f.ns == 3 ? 1 : -1);
             if (src != s) continue;
             const double dist = d == 0 ? cx + 0.5 - x1 : d == 1 ? cy + 0.5 - y1
@@ -228,6 +222,32 @@ __device__ int move(const Field &f, uint64_t id, uint64_t t, double buf_hi, doub
             }
         }
     }
+    return ds;
+}
+
+// One step of one particle; returns the signed crossing of x = plane.
+__device__ int move(const Field &f, uint64_t id, uint64_t t, double buf_hi, double plane,
+                    double &x, double &y, uint8_t &s)
+{
+    const double x0 = x, y0 = y;
+    const int ox = cell_of(x0), oy = cell_of(y0);
+    // one load gives every cell type the step needs (in all but steps longer
+    // than a cell); it and the corner velocities are the step's gathers
+    const Window wv = window_at(f, ox, oy);
+    double u, v;
+    interp2(f, wv, x0, y0, u, v);
+    u *= f.vs;
+    v *= f.vs;
+    double sn, cs;
+    sincos(2.0 * M_PI * draw(f.seed, id, t, 0), &sn, &cs);
+    double x1 = x0 + u * f.dt + f.len * cs;
+    double y1 = y0 + v * f.dt + f.len * sn;
+    const int lx = cell_of(x1) - ox, ly = cell_of(y1) - oy;
+    int ds;
+    if (lx >= -1 && lx <= 1 && ly >= -1 && ly <= 1)
+        ds = finish(f, WinTypes{wv}, id, t, buf_hi, plane, x0, y0, x1, y1, s);
+    else
+        ds = finish(f, ReadTypes{f}, id, t, buf_hi, plane, x0, y0, x1, y1, s);
     x = x1;
     y = y1;
     return ds;
@@ -428,25 +448,20 @@ __global__ __launch_bounds__(256) void k_move(Field f, Parts p, Scalars *sc, dou
 
 __global__ void k_tick(Scalars *sc) { sc->t += 1; }
 
-// Per cell: the velocity pair, and the types of the 3 x 3 cells around it
-// (bits 2 (3 (dy + 1) + dx + 1)), with solid()'s convention outside.
-__global__ void k_pack_fields(Field f, const double *ux, const double *uy, double2 *uv, uint32_t *nb)
+// Per cell: the velocity pair; per cell (ox, oy) of [-3, nx + 3) x
+// [-3, ny + 3): the types of the 5 x 5 cells around it (bits
+// 2 (5 (dy + 2) + dx + 2)), outside the lattice as type_read.
+__global__ void k_pack_fields(Field f, const double *ux, const double *uy, double2 *uv, uint64_t *nb)
 {
-    const long long n = (long long)f.nx * f.ny;
-    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+    const long long n = (long long)f.nx * f.ny, nw = (long long)(f.nx + 6) * (f.ny + 6);
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < nw;
          c += (long long)gridDim.x * blockDim.x) {
-        const int x = (int)(c % f.nx), y = (int)(c / f.nx);
-        uv[c] = make_double2(ux[c], uy[c]);
-        uint32_t w = 0;
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int sx = x + dx, sy = y + dy;
-                uint32_t t;
-                if (sy < 0 || sy >= f.ny) t = 1;
-                else if (sx < 0 || sx >= f.nx) t = 0;
-                else t = f.type[(size_t)sy * f.nx + sx];
-                w |= t << (2 * (3 * (dy + 1) + dx + 1));
-            }
+        if (c < n) uv[c] = make_double2(ux[c], uy[c]);
+        const int ox = (int)(c % (f.nx + 6)) - 3, oy = (int)(c / (f.nx + 6)) - 3;
+        uint64_t w = 0;
+        for (int dy = -2; dy <= 2; ++dy)
+            for (int dx = -2; dx <= 2; ++dx)
+                w |= (uint64_t)type_read(f, ox + dx, oy + dy) << (2 * (5 * (dy + 2) + dx + 2));
         nb[c] = w;
     }
 }
@@ -592,7 +607,7 @@ void layout(Rw *r)
     };
     r->off.type = take(n);
     r->off.uv = take(16 * n);
-    r->off.nb = take(4 * n);
+    r->off.nb = take(8 * ((size_t)r->p.nx + 6) * ((size_t)r->p.ny + 6));
     r->off.k = take(8 * n);
     for (int b = 0; b < 2; ++b) {
         r->off.x[b] = take(8 * C);
@@ -617,7 +632,7 @@ Field field(Rw *r)
     f.wall_mode = r->p.wall_mode;
     f.type = (const uint8_t *)r->ptr(r->off.type);
     f.uv = (const double2 *)r->ptr(r->off.uv);
-    f.nb = (const uint32_t *)r->ptr(r->off.nb);
+    f.nb = (const uint64_t *)r->ptr(r->off.nb);
     f.k = (const double *)r->ptr(r->off.k);
     f.vs = r->p.vel_scale;
     f.dt = r->p.dt;
@@ -814,9 +829,10 @@ lbf_status lbf_rw_set_fields(lbf_rw r, const uint8_t *type, const double *ux, co
     for (int i = 0; i < 2 && e == hipSuccess; ++i)
         e = hipMemcpyAsync(r->ptr(off[i]), src[i], bytes[i], hipMemcpyDeviceToDevice, r->stream);
     if (e != hipSuccess) return hip_fail(r, e, "copy fields");
-    const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+    const size_t nw = ((size_t)r->p.nx + 6) * ((size_t)r->p.ny + 6);
+    const unsigned blocks = (unsigned)std::min<size_t>((nw + 255) / 256, 4096);
     hipLaunchKernelGGL(k_pack_fields, dim3(blocks), dim3(256), 0, r->stream, field(r), ux, uy,
-                       (double2 *)r->ptr(r->off.uv), (uint32_t *)r->ptr(r->off.nb));
+                       (double2 *)r->ptr(r->off.uv), (uint64_t *)r->ptr(r->off.nb));
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(r, e, "pack fields");
     r->fields_set = true;

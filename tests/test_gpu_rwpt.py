@@ -43,8 +43,11 @@ def _start(w, n, seed):
     return ids, x, y
 
 
-@pytest.mark.parametrize("name,ns,vel_scale", [("rw", 2, 1.0), ("tiny", 3, 4.0)])
+@pytest.mark.parametrize("name,ns,vel_scale", [("rw", 2, 1.0), ("tiny", 3, 4.0), ("tiny", 3, 60.0)])
 def test_trajectories_match_oracle(flows, name, ns, vel_scale):
+    # vel_scale 60: advection moves up to 1.5 cells per step, beyond the 5 x 5
+    # window of cell types the GPU step reads at once, so its direct reads of
+    # the cells outside the window are exercised as well
     L = _lbf()
     w, ux, uy = flows[name]
     D = w.params.d
@@ -61,7 +64,7 @@ def test_trajectories_match_oracle(flows, name, ns, vel_scale):
     xg, yg, sg = r.walk(ids, x, y, sp, 3, steps)
     xg, yg, sg = xg.cpu().numpy(), yg.cpu().numpy(), sg.cpu().numpy()
     r.close()
-    assert (so > 0).mean() > 0.02                    # reactions happened
+    assert (so > 0).mean() > (0.02 if vel_scale < 10 else 0.002)  # reactions happened
     d = np.abs(xg - xo) + np.abs(yg - yo)
     off = (d > 1e-9) | (sg != so)
     assert off.mean() <= 1e-3, off.mean()
