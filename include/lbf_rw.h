@@ -65,8 +65,8 @@ lbf_status lbf_rw_bind(lbf_rw rw, void *workspace_dev, size_t bytes, void *hip_s
 /* Geometry and fields (device arrays [ny][nx], copied): node_type u8 with
  * values 0..3, flow velocity ux, uy and rates k as double.  Rows 0 and ny-1
  * must be solid (LBF_EINVAL otherwise).  The copy interleaves ux and uy and
- * keeps per cell the types of the 3 x 3 cells around it, so a particle step
- * reads each corner velocity and a whole neighbourhood of types in one load. */
+ * keeps per cell the types of the 5 x 5 cells around it, so a particle step
+ * reads each corner velocity, and every cell type it needs, in one load. */
 lbf_status lbf_rw_set_fields(lbf_rw rw, const uint8_t *node_type_dev, const double *ux_dev,
                              const double *uy_dev, const double *k_dev);
 /* Uniform A at `density` in every fluid cell; resets the step and the
