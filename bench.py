@@ -21,6 +21,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -290,8 +291,9 @@ def membrane3d_leg(steps=2000):
 def rwpt_leg(w, ux, uy, steps=200, density=10.0):
     """The GPU random-walk tracker on the same geometry and flow as the
     headline ADR run: particle-steps per second and the bytes a step moves
-    per particle (move: 25 B read + 17 B written; compaction, once per 16
-    steps: 8 B read to count, 25 B read + 25 B written to scatter)."""
+    per particle (move: 25 B read + 17 B written; compaction, at the start of
+    each 200-step graph block and every min(64, nx / 8) steps inside it: 8 B
+    read to count, 25 B read + 25 B written to scatter)."""
     import torch
     import paper_2109_04455_amd as L
     p = L.rw_params(w.nx, w.ny, nspecies=w.nspecies, D=w.params.d, vel_scale=w.vel_scale,
@@ -304,7 +306,8 @@ def rwpt_leg(w, ux, uy, steps=200, density=10.0):
     n, held, _ = r.counts()
     r.close()
     per_step = ms * 1e-3 / steps
-    bytes_pp = 42 + (8 + 50) / 16
+    every = min(64, max(1, w.nx // 8))
+    bytes_pp = 42 + (8 + 50) * math.ceil(200 / every) / 200
     return {"workload": f"{w.name} geometry and flow, density {density} per unit area",
             "particles": held, "steps": steps, "us_per_step": round(per_step * 1e6, 1),
             "particle_steps_per_s": round(held / per_step, 1),

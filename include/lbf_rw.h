@@ -55,7 +55,8 @@ typedef struct {
     uint64_t seed;
     long capacity;       /* maximum number of particles held (the particles that
                             left stay in the arrays until the next compaction,
-                            at most 16 steps' worth)                            */
+                            at most min(64, nx / 8) steps' worth, about an
+                            eighth of the particles the domain holds)          */
 } lbf_rw_params;
 
 lbf_status lbf_rw_params_default(lbf_rw_params *p, int nx, int ny);

@@ -24,9 +24,12 @@ constexpr uint64_t ID_INSERT = 1ULL << 62;
 constexpr uint64_t ID_COUNT = 1ULL << 63;
 constexpr int SCAN_BLOCKS = 1024;  // blocks of every scan pass (fixed: sizes are on the device)
 constexpr int SCAN_THREADS = 256;
-// the arrays are compacted every COMPACT_EVERY steps of a graph block; in
-// between, particles that left stay in place (skipped by the move)
-constexpr long COMPACT_EVERY = 16;
+// the arrays are compacted at the start of every graph block and every
+// compact_every steps inside one (nx / 8, between 1 and 64: a step inserts
+// about 1/nx of the particles the domain holds, so the slots of those that
+// left in between stay within an eighth of them); in between, particles that
+// left stay in place (skipped by the move)
+constexpr long COMPACT_MAX = 64;
 constexpr double BUF_LO = -1.5, BUF_HI = -0.5;  // reservoir strip
 
 __device__ __forceinline__ uint64_t mix(uint64_t z)
@@ -575,6 +578,7 @@ struct lbf_rw_s {
     long long buf_count = 0;
     long measured = 0;
     int xf = 0;
+    long compact_every = 1;
     std::map<std::tuple<long, int, int>, hipGraphExec_t> graphs;
     void *ptr(size_t o) const { return ws + o; }
 };
@@ -687,7 +691,7 @@ lbf_status run_block(Rw *r, long n, int measure)
         int p = r->par;
         hipError_t le = hipSuccess;
         for (long i = 0; i < n && le == hipSuccess; ++i) {
-            const bool compact = i % COMPACT_EVERY == 0;
+            const bool compact = i % r->compact_every == 0;
             le = enqueue_step(r, p, measure, compact, r->cap_stream);
             if (compact) p ^= 1;
         }
@@ -706,7 +710,7 @@ lbf_status run_block(Rw *r, long n, int measure)
     }
     hipError_t e = hipGraphLaunch(it->second, r->stream);
     if (e != hipSuccess) return hip_fail(r, e, "hipGraphLaunch");
-    if (((n + COMPACT_EVERY - 1) / COMPACT_EVERY) & 1) r->par ^= 1;  // one swap per compaction
+    if (((n + r->compact_every - 1) / r->compact_every) & 1) r->par ^= 1;  // one swap per compaction
     return LBF_OK;
 }
 
@@ -776,6 +780,7 @@ lbf_status lbf_rw_create(const lbf_rw_params *p, lbf_rw *out)
     if (!why.empty()) return fail(r, LBF_EINVAL, why);
     r->p = *p;
     r->xf = p->xf == -1 ? p->nx - 3 : p->xf;
+    r->compact_every = std::min<long>(COMPACT_MAX, std::max<long>(1, p->nx / 8));
     r->buf_count = std::lround(p->density * (BUF_HI - BUF_LO) * ((p->ny - 1.5) - 0.5));
     layout(r);
     r->valid = true;

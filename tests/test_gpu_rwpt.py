@@ -95,9 +95,10 @@ def test_full_run_crossing_counts_match_oracle(flows):
 
 
 def test_graph_blocks_do_not_change_results(flows):
-    # the compactions fall at the start of every captured block and every 16
-    # steps inside one: one-step blocks compact every step, the others every
-    # 7 or 16 steps, with the same crossings and particle counts
+    # the compactions fall at the start of every captured block and every
+    # nx / 8 steps inside one (12 on this 96-wide lattice): one-step blocks
+    # compact every step, the others every 7 or 12 steps, with the same
+    # crossings and particle counts
     L = _lbf()
     w, ux, uy = flows["rw"]
     out = []
