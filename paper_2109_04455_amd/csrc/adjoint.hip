@@ -20,6 +20,7 @@
 #include <cmath>
 #include <vector>
 
+#include "adr_device.hpp"
 #include "ctx.hpp"
 #include "stencil.hpp"
 
@@ -45,12 +46,99 @@ struct AdjArgs {
     const Real *kr;
     const int32_t *trace_idx;
     const Real *trace;    // (C_A, C_B) of step m at the trace nodes
+    const Real *trace2;   // two-step launches: the same for step m - 1
     double *acc;          // [ntrace][4] per-link gradient accumulators
     int nx, ny, nxp;
     size_t plane;
     Real omega;
     Launch L;
 };
+
+// The gather of one adjoint step at node x: lam(m) from nu(m+1).  blk_of(s)
+// addresses species s's 5 planes with byte offsets: PB between planes, RB
+// between rows, o the node's own.
+template <typename Real, int S, typename BlkOf, typename Off>
+__device__ __forceinline__ void adj_gather(const BlkOf &blk_of, Off PB, Off RB, Off o, int x,
+                                           int nx, unsigned m, Real (&lam)[S][5])
+{
+    constexpr Off B = sizeof(Real);
+    const Off oE = o + DE * PB, oN = o + DN * PB, oW = o + DW * PB, oS = o + DS * PB;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const auto nu = blk_of(s);
+        lam[s][0] = nu.load(o);
+        // z_E(x) feeds g_E(x+1), or g_W(x) by bounce-back, or the outlet rule
+        if (x == nx - 1)
+            lam[s][DE] = -nu.load(oW);
+        else
+            lam[s][DE] = nu.load((m & BIT_E) ? oW : oE + B);
+        lam[s][DN] = nu.load((m & BIT_N) ? oS : oN + RB);
+        // z_W(x) feeds g_W(x-1), or g_E(x) by bounce-back / the inlet rule
+        if (x == 0)
+            lam[s][DW] = s == 0 ? -nu.load(oE) : nu.load(oE);
+        else
+            lam[s][DW] = nu.load((m & BIT_W) ? oE : oW - B);
+        lam[s][DS] = nu.load((m & BIT_S) ? oN : oS - RB);
+        if (x == nx - 1) {
+            // outlet: every post-collision population enters C_b of g_W
+            const Real ow = Real(2) * w5<Real>(DW) * nu.load(oW);
+#pragma unroll
+            for (int i = 0; i < 5; ++i) lam[s][i] += ow;
+        }
+    }
+}
+
+// The local part of one adjoint step at fluid node id: the gradient terms of
+// its catalytic links (added to the accumulators when `own`), then
+// nu(m) = (R Col)^T lam into out.  trace: (C_A, C_B) of step m.
+template <typename Real, int S>
+__device__ __forceinline__ void adj_local(const AdjArgs<Real> &a, const Real *trace, size_t id,
+                                          unsigned m, Real u, Real v, bool own,
+                                          const Real (&lam)[S][5], Real (&out)[S][5])
+{
+    Real rsrc[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) rsrc[s] = 0;
+    if (m & 0xF0u) {
+        const int off[5] = {0, 1, a.nxp, -1, -a.nxp};
+        const int t = a.trace_idx[id];
+        const Real ca = trace[2 * t], cb = trace[2 * t + 1];
+#pragma unroll
+        for (int i = 1; i < 5; ++i) {
+            if (!((m >> (3 + i)) & 1u)) continue;
+            const size_t sid = id + off[i];
+            const Real kap = a.kr[sid] * w5<Real>(i);
+            double g;
+            if (a.type[sid] == 2) {
+                const Real d = lam[1][i] - lam[0][i];
+                g = (double)w5<Real>(i) * (double)ca * (double)d;
+                rsrc[0] += kap * d;
+            } else {
+                const Real d = lam[S - 1][i] - lam[1][i];
+                g = (double)w5<Real>(i) * (double)cb * (double)d;
+                rsrc[1] += kap * d;
+            }
+            if (own) a.acc[4 * t + i - 1] += g;
+        }
+    }
+    // (R Col)^T: nu_j = (1 - omega) lam_j + omega sum_i e_i lam_i + rsrc
+    const Real uu = Real(1.5) * (u * u + v * v);
+    Real e[5];
+    e[0] = w5<Real>(0) * (Real(1) - uu);
+    e[DE] = w5<Real>(DE) * (Real(1) + Real(3) * u + Real(4.5) * u * u - uu);
+    e[DN] = w5<Real>(DN) * (Real(1) + Real(3) * v + Real(4.5) * v * v - uu);
+    e[DW] = w5<Real>(DW) * (Real(1) - Real(3) * u + Real(4.5) * u * u - uu);
+    e[DS] = w5<Real>(DS) * (Real(1) - Real(3) * v + Real(4.5) * v * v - uu);
+    const Real keep = Real(1) - a.omega;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const Real M = e[0] * lam[s][0] + e[1] * lam[s][1] + e[2] * lam[s][2] + e[3] * lam[s][3] +
+                       e[4] * lam[s][4];
+        const Real add = a.omega * M + rsrc[s];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) out[s][i] = keep * lam[s][i] + add;
+    }
+}
 
 // One adjoint step at node x for all species.
 template <typename Real, int S, bool NT, bool WIDE>
@@ -67,75 +155,109 @@ __global__ __launch_bounds__(1024) void k_adjoint_step(AdjArgs<Real> a)
     using Off = off_t_<WIDE>;
     constexpr Off B = sizeof(Real);
     const Off PB = (Off)P * B, RB = (Off)a.nxp * B, o = (Off)id * B;
-    const Off oE = o + DE * PB, oN = o + DN * PB, oW = o + DW * PB, oS = o + DS * PB;
+    const auto nu = [&](int s) { return PopBlock<Real, NT, WIDE>(a.nu_src + (size_t)s * 5 * P, 5 * PB); };
     Real lam[S][5];
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        const PopBlock<Real, NT, WIDE> nu(a.nu_src + (size_t)s * 5 * P, 5 * PB);
-        lam[s][0] = nu.load(o);
-        // z_E(x) feeds g_E(x+1), or g_W(x) by bounce-back, or the outlet rule
-        if (x == a.nx - 1)
-            lam[s][DE] = -nu.load(oW);
-        else
-            lam[s][DE] = nu.load((m & BIT_E) ? oW : oE + B);
-        lam[s][DN] = nu.load((m & BIT_N) ? oS : oN + RB);
-        // z_W(x) feeds g_W(x-1), or g_E(x) by bounce-back / the inlet rule
-        if (x == 0)
-            lam[s][DW] = s == 0 ? -nu.load(oE) : nu.load(oE);
-        else
-            lam[s][DW] = nu.load((m & BIT_W) ? oE : oW - B);
-        lam[s][DS] = nu.load((m & BIT_S) ? oN : oS - RB);
-        if (x == a.nx - 1) {
-            // outlet: every post-collision population enters C_b of g_W
-            const Real ow = Real(2) * w5<Real>(DW) * nu.load(oW);
-#pragma unroll
-            for (int i = 0; i < 5; ++i) lam[s][i] += ow;
-        }
-    }
-    Real rsrc[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) rsrc[s] = 0;
-    if (m & 0xF0u) {
-        const int off[5] = {0, 1, a.nxp, -1, -a.nxp};
-        const int t = a.trace_idx[id];
-        const Real ca = a.trace[2 * t], cb = a.trace[2 * t + 1];
-#pragma unroll
-        for (int i = 1; i < 5; ++i) {
-            if (!((m >> (3 + i)) & 1u)) continue;
-            const size_t sid = id + off[i];
-            const Real kap = a.kr[sid] * w5<Real>(i);
-            double g;
-            if (a.type[sid] == 2) {
-                const Real d = lam[1][i] - lam[0][i];
-                g = (double)w5<Real>(i) * (double)ca * (double)d;
-                rsrc[0] += kap * d;
-            } else {
-                const Real d = lam[S - 1][i] - lam[1][i];
-                g = (double)w5<Real>(i) * (double)cb * (double)d;
-                rsrc[1] += kap * d;
-            }
-            a.acc[4 * t + i - 1] += g;
-        }
-    }
-    // (R Col)^T: nu_j = (1 - omega) lam_j + omega sum_i e_i lam_i + rsrc
+    adj_gather<Real, S>(nu, PB, RB, o, x, a.nx, m, lam);
     const PopBlock<Real, false, WIDE> vel(a.ua, 2 * PB);
-    const Real u = vel.load(o), v = vel.load(o + PB);
-    const Real uu = Real(1.5) * (u * u + v * v);
-    Real e[5];
-    e[0] = w5<Real>(0) * (Real(1) - uu);
-    e[DE] = w5<Real>(DE) * (Real(1) + Real(3) * u + Real(4.5) * u * u - uu);
-    e[DN] = w5<Real>(DN) * (Real(1) + Real(3) * v + Real(4.5) * v * v - uu);
-    e[DW] = w5<Real>(DW) * (Real(1) - Real(3) * u + Real(4.5) * u * u - uu);
-    e[DS] = w5<Real>(DS) * (Real(1) - Real(3) * v + Real(4.5) * v * v - uu);
-    const Real keep = Real(1) - a.omega;
+    Real out[S][5];
+    adj_local<Real, S>(a, a.trace, id, m, vel.load(o), vel.load(o + PB), true, lam, out);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        const Real M = e[0] * lam[s][0] + e[1] * lam[s][1] + e[2] * lam[s][2] + e[3] * lam[s][3] +
-                       e[4] * lam[s][4];
-        const Real add = a.omega * M + rsrc[s];
-        const PopBlock<Real, NT, WIDE> out(a.nu_dst + (size_t)s * 5 * P, 5 * PB);
+        const PopBlock<Real, NT, WIDE> dst(a.nu_dst + (size_t)s * 5 * P, 5 * PB);
 #pragma unroll
-        for (int i = 0; i < 5; ++i) out.store(o + i * PB, keep * lam[s][i] + add);
+        for (int i = 0; i < 5; ++i) dst.store(o + i * PB, out[s][i]);
+    }
+}
+
+// Two adjoint steps per launch (m, then m - 1), the tiling of the forward
+// two-step launch: step m updates the extended tile (output nodes and a
+// one-node ring) from nu(m+1) in HBM into LDS; step m - 1 gathers the output
+// nodes from LDS and writes nu(m-1).  Gradient terms are added by the block
+// owning the node only (ring nodes are computed by every block they border),
+// in the order of two single steps.  Masks and velocities stay in LDS with
+// FP32 state, as in the forward.
+template <typename Real, int S, bool NT, bool WIDE>
+__global__ __launch_bounds__(64 * (adr::PairTile<Real>::EY + 1))
+__attribute__((amdgpu_waves_per_eu(adr::PairTile<Real>::OCC))) void k_adjoint_step2(AdjArgs<Real> a)
+{
+    constexpr int EY = adr::PairTile<Real>::EY, EX = 66, TY = EY - 2, EP = EX * EY;
+    constexpr bool ULDS = adr::PairTile<Real>::ULDS;
+    __shared__ Real lds[5 * S * EP];
+    __shared__ Real lvel[ULDS ? 2 * EP : 1];
+    __shared__ uint8_t lmask[ULDS ? EP : 1];
+    using Off = off_t_<WIDE>;
+    constexpr Off B = sizeof(Real);
+    int bx, by;
+    tile_of_block(a.L, bx, by);
+    const int x0 = bx * 64, y0 = by * TY;  // first output node
+    const int w = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
+    const size_t P = a.plane;
+    const Off PB = (Off)P * B;
+    {
+        const bool ring = w >= EY;
+        const int ex = ring ? ((lane & 1) ? EX - 1 : 0) : lane + 1, ey = ring ? lane >> 1 : w;
+        const int x = x0 - 1 + ex, y = y0 - 1 + ey;
+        if (ey < EY && x >= 0 && x < a.nx && y >= 0 && y < a.ny) {
+            const size_t id = (size_t)y * a.nxp + x;
+            const int e = ey * EX + ex;
+            const unsigned m = a.mask5[id];
+            if (ULDS) lmask[e] = (uint8_t)m;
+            if (m != MASK5_SOLID) {
+                const Off o = (Off)id * B;
+                const auto nu = [&](int s) {
+                    return PopBlock<Real, false, WIDE>(a.nu_src + (size_t)s * 5 * P, 5 * PB);
+                };
+                Real lam[S][5];
+                adj_gather<Real, S>(nu, PB, (Off)a.nxp * B, o, x, a.nx, m, lam);
+                const PopBlock<Real, false, WIDE> vel(a.ua, 2 * PB);
+                const Real u = vel.load(o), v = vel.load(o + PB);
+                if (ULDS) {
+                    lvel[e] = u;
+                    lvel[EP + e] = v;
+                }
+                const bool own = ex >= 1 && ex <= 64 && ey >= 1 && ey <= TY;
+                Real out[S][5];
+                adj_local<Real, S>(a, a.trace, id, m, u, v, own, lam, out);
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+#pragma unroll
+                    for (int i = 0; i < 5; ++i) lds[(s * 5 + i) * EP + e] = out[s][i];
+            }
+        }
+    }
+    __syncthreads();
+    // Step m - 1 on the output rows.  The ring nodes a gather can reach
+    // (x - 1 for x > 0, x + 1 for x < nx - 1, y +- 1 of a fluid node) were
+    // all updated above.
+    if (w >= TY) return;
+    const int x = x0 + lane, y = y0 + w;
+    if (x >= a.nx || y >= a.ny) return;
+    const size_t id = (size_t)y * a.nxp + x;
+    const int e = (w + 1) * EX + lane + 1;
+    const unsigned m = ULDS ? lmask[e] : a.mask5[id];
+    if (m == MASK5_SOLID) return;
+    constexpr uint32_t LB = sizeof(Real);
+    const auto nu = [&](int s) { return LdsBlock<Real>{lds + s * 5 * EP}; };
+    Real lam[S][5];
+    adj_gather<Real, S>(nu, (uint32_t)(EP * LB), (uint32_t)(EX * LB), (uint32_t)e * LB, x, a.nx, m,
+                        lam);
+    const Off o = (Off)id * B;
+    Real u, v;
+    if (ULDS) {
+        u = lvel[e];
+        v = lvel[EP + e];
+    } else {
+        const PopBlock<Real, false, WIDE> vel(a.ua, 2 * PB);
+        u = vel.load(o);
+        v = vel.load(o + PB);
+    }
+    Real out[S][5];
+    adj_local<Real, S>(a, a.trace2, id, m, u, v, true, lam, out);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const PopBlock<Real, NT, WIDE> dst(a.nu_dst + (size_t)s * 5 * P, 5 * PB);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) dst.store(o + i * PB, out[s][i]);
     }
 }
 
@@ -265,6 +387,41 @@ hipError_t launch_adjoint_step(Ctx *c, const void *nu_src, void *nu_dst, const v
         adjoint_launch(c, adj_args<float>(c, nu_src, nu_dst, trace, acc), s);
     else
         adjoint_launch(c, adj_args<double>(c, nu_src, nu_dst, trace, acc), s);
+    return hipGetLastError();
+}
+
+template <typename Real>
+void adjoint_pair_launch(Ctx *c, const AdjArgs<Real> &a, hipStream_t s)
+{
+    const dim3 g = c->Lp.grid(), b(64 * (adr::PairTile<Real>::EY + 1));
+    const int sel = (c->Lp.nontemporal ? 1 : 0) | (c->Lp.wide ? 2 : 0) | (c->p.nspecies == 3 ? 4 : 0);
+    switch (sel) {
+    case 0: hipLaunchKernelGGL((k_adjoint_step2<Real, 2, false, false>), g, b, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_adjoint_step2<Real, 2, true, false>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_adjoint_step2<Real, 2, false, true>), g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_adjoint_step2<Real, 2, true, true>), g, b, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_adjoint_step2<Real, 3, false, false>), g, b, 0, s, a); break;
+    case 5: hipLaunchKernelGGL((k_adjoint_step2<Real, 3, true, false>), g, b, 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_adjoint_step2<Real, 3, false, true>), g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_adjoint_step2<Real, 3, true, true>), g, b, 0, s, a); break;
+    }
+}
+
+// Adjoint steps m and m - 1 in one launch: nu(m+1) -> nu(m-1).
+hipError_t launch_adjoint_pair(Ctx *c, const void *nu_src, void *nu_dst, const void *trace_m,
+                               const void *trace_m1, double *acc, hipStream_t s)
+{
+    if (c->p.real_bytes == 4) {
+        AdjArgs<float> a = adj_args<float>(c, nu_src, nu_dst, trace_m, acc);
+        a.trace2 = (const float *)trace_m1;
+        a.L = c->Lp;
+        adjoint_pair_launch(c, a, s);
+    } else {
+        AdjArgs<double> a = adj_args<double>(c, nu_src, nu_dst, trace_m, acc);
+        a.trace2 = (const double *)trace_m1;
+        a.L = c->Lp;
+        adjoint_pair_launch(c, a, s);
+    }
     return hipGetLastError();
 }
 
@@ -455,11 +612,16 @@ lbf_status lbf_adr_adjoint(lbf_ctx c, long T, int M, int keep, void *ws, size_t 
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "adjoint seed");
     int cur = 0;
+    // adjoint steps run two per launch (m and m - 1) within a trace window
     if (keep) {
-        for (long m = T - 1; m >= 0; --m) {
-            e = launch_adjoint_step(c, nu[cur], nu[cur ^ 1], slot(L.trace, m), acc, s);
+        for (long m = T - 1; m >= 0;) {
+            const bool two = c->pair && m >= 1;
+            e = two ? launch_adjoint_pair(c, nu[cur], nu[cur ^ 1], slot(L.trace, m),
+                                          slot(L.trace, m - 1), acc, s)
+                    : launch_adjoint_step(c, nu[cur], nu[cur ^ 1], slot(L.trace, m), acc, s);
             if (e != hipSuccess) return hip_fail(c, e, "adjoint step");
             cur ^= 1;
+            m -= two ? 2 : 1;
         }
     } else {
         void *rec[2] = {W + L.rec[0], W + L.rec[1]};
@@ -479,10 +641,14 @@ lbf_status lbf_adr_adjoint(lbf_ctx c, long T, int M, int keep, void *ws, size_t 
                 r ^= 1;
                 q += two ? 2 : 1;
             }
-            for (long m = a1 - 1; m >= a0; --m) {
-                e = launch_adjoint_step(c, nu[cur], nu[cur ^ 1], slot(L.trace, m - a0), acc, s);
+            for (long m = a1 - 1; m >= a0;) {
+                const bool two = c->pair && m - 1 >= a0;
+                e = two ? launch_adjoint_pair(c, nu[cur], nu[cur ^ 1], slot(L.trace, m - a0),
+                                              slot(L.trace, m - 1 - a0), acc, s)
+                        : launch_adjoint_step(c, nu[cur], nu[cur ^ 1], slot(L.trace, m - a0), acc, s);
                 if (e != hipSuccess) return hip_fail(c, e, "adjoint step");
                 cur ^= 1;
+                m -= two ? 2 : 1;
             }
         }
     }

@@ -58,6 +58,33 @@ def test_adjoint_matches_autograd(tiny_ref, real, tol, keep, ckpt):
     assert abs(c.efficiency()[0] - eps) <= 1e-12 * abs(eps)
 
 
+@pytest.mark.parametrize("real,tol", [("f64", 1e-11), ("f32", 1e-4)])
+@pytest.mark.parametrize("keep,ckpt", [(True, 200), (False, 201)])
+def test_two_step_adjoint_equals_single_steps(tiny_ref, real, tol, keep, ckpt):
+    # adjoint steps run two per launch by default; flags bit 8 runs every
+    # step, forward and adjoint, one per launch.  T = 999 and 201-step
+    # segments leave single steps at the window's and the segments' ends.
+    # The per-node arithmetic is the same code compiled into other kernels
+    # (multiply-adds fused per kernel), so results agree to round-off
+    w, flow_steps, n0, _, _, _ = tiny_ref
+    out = []
+    for flags in (0, 256):
+        c = _ctx(w, real, flags=flags)
+        c.flow_init()
+        c.flow_run(flow_steps)
+        c.adr_init()
+        c.adr_run(n0, tol=0)
+        eps, grad = c.adjoint(999, ckpt_every=ckpt, keep_trace=keep)
+        out.append((eps, grad.cpu().numpy()))
+        c.close()
+    (e2, g2), (e1, g1) = out
+    scale = np.abs(g1).max()
+    assert scale > 0
+    print(real, keep, "max |two-step - one-step| / max |grad|", np.abs(g2 - g1).max() / scale, flush=True)
+    assert np.abs(g2 - g1).max() <= tol * scale
+    assert abs(e2 / e1 - 1) <= tol
+
+
 def test_adjoint_long_window_tends_to_steady_adjoint():
     w = make_workload("tiny")
     ux, uy, _, _ = R.flow_steady(w.node_type, w.tau_f, w.u0, 3000, tol=0)
