@@ -265,8 +265,9 @@ struct Parts {
 // Scalars kept on the device (so that a step needs no host round trip).
 struct Scalars {
     long long n_cur;     // particles in the current arrays
-    long long n_alive;   // survivors of the last compaction
-    long long t;         // step counter
+    long long n_alive;   // this step's insertion point (survivors of a compaction)
+    long long t;         // this step's number
+    long long t_next;    // the next step's number
     long long cross[3];  // signed crossings while measuring
     long long n_held;    // particles moved by the last step
     int overflow;        // capacity was hit
@@ -399,16 +400,19 @@ __global__ void k_insert(Parts dst, Scalars *sc, long long buf_count, long long 
     }
 }
 
-__global__ void k_set_count(Scalars *sc, long long buf_count, long long capacity)
+// Start of a step: its number, its insertion point (a step without
+// compaction appends after every particle of the arrays, the ones that left
+// since the last compaction included) and its particle count with the
+// reservoir refill.
+__global__ void k_step_begin(Scalars *sc, long long buf_count, long long capacity, int lazy)
 {
+    if (lazy) sc->n_alive = sc->n_cur;
     const long long n = sc->n_alive + buf_count;
     sc->n_cur = n < capacity ? n : capacity;
     sc->n_held = 0;
+    sc->t = sc->t_next;
+    sc->t_next = sc->t + 1;
 }
-
-// A step without compaction appends its new particles after every particle
-// of the arrays, the ones that left since the last compaction included.
-__global__ void k_lazy_base(Scalars *sc) { sc->n_alive = sc->n_cur; }
 
 // move every particle; crossing counts reduced per block, then one atomic
 // per block and species.  Particles below this step's insertion point
@@ -449,7 +453,6 @@ __global__ __launch_bounds__(256) void k_move(Field f, Parts p, Scalars *sc, dou
         atomicAdd((unsigned long long *)&sc->n_held, (unsigned long long)cnt[3]);
 }
 
-__global__ void k_tick(Scalars *sc) { sc->t += 1; }
 
 // Per cell: the velocity pair; per cell (ox, oy) of [-3, nx + 3) x
 // [-3, ny + 3): the types of the 5 x 5 cells around it (bits
@@ -541,7 +544,7 @@ __global__ void k_fill_finish(Scalars *sc, const long long *total, long long cap
     const long long n = *total;
     sc->n_cur = n < capacity ? n : capacity;
     sc->n_alive = 0;
-    sc->t = 0;
+    sc->t = sc->t_next = 0;
     sc->cross[0] = sc->cross[1] = sc->cross[2] = 0;
     sc->n_held = sc->n_cur;
 }
@@ -667,16 +670,13 @@ hipError_t enqueue_step(Rw *r, int par, int measure, bool compact, hipStream_t s
         hipLaunchKernelGGL(k_count_alive, dim3(SCAN_BLOCKS), dim3(SCAN_THREADS), 0, s, src, sc, r->p.nx, bsum);
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_BLOCKS), 0, s, bsum, boff, &sc->n_alive);
         hipLaunchKernelGGL(k_compact, dim3(SCAN_BLOCKS), dim3(SCAN_THREADS), 0, s, src, dst, sc, r->p.nx, boff);
-    } else {
-        hipLaunchKernelGGL(k_lazy_base, dim3(1), dim3(1), 0, s, sc);
     }
+    hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(1), 0, s, sc, r->buf_count, C, compact ? 0 : 1);
     hipLaunchKernelGGL(k_insert, dim3(64), dim3(256), 0, s, dst, sc, r->buf_count, C, r->p.seed,
                        0.5, r->p.ny - 1.5);
-    hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, s, sc, r->buf_count, C);
     const long long gmax = (C + 255) / 256;
     const unsigned grid = (unsigned)(gmax < 8192 ? (gmax > 0 ? gmax : 1) : 8192);
     hipLaunchKernelGGL(k_move, dim3(grid), dim3(256), 0, s, field(r), dst, sc, r->xf + 0.5, measure);
-    hipLaunchKernelGGL(k_tick, dim3(1), dim3(1), 0, s, sc);
     return hipGetLastError();
 }
 
