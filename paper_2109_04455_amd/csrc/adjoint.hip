@@ -705,6 +705,12 @@ lbf_status lbf_adr_adjoint_steady(lbf_ctx c, long max_iters, int check_every, do
     double dfdn[3] = {0, 0, 0};
     for (int q = 0; q < ns; ++q) dfdn[q] = -o[ns - 1] / (tot * tot) + (q == ns - 1 ? 1.0 / tot : 0.0);
     void *nu[2] = {W + L.nu[0], W + L.nu[1]};
+    // the steps write fluid nodes only and the norm reads every entry: start
+    // the second lattice at zero (the seed writes all of the first)
+    {
+        hipError_t e0 = hipMemsetAsync(nu[1], 0, L.lattice, s);
+        if (e0 != hipSuccess) return hip_fail(c, e0, "adjoint lattice clear");
+    }
     if (c->p.real_bytes == 4)
         hipLaunchKernelGGL(k_adjoint_seed<float>, dim3(2048), dim3(256), 0, s, (float *)nu[0],
                            (const uint8_t *)c->ptr(c->off.mask5), ns, c->p.nx, c->p.ny, c->nxp,
@@ -739,10 +745,14 @@ lbf_status lbf_adr_adjoint_steady(lbf_ctx c, long max_iters, int check_every, do
     bool conv = false;
     while (it < max_iters) {
         const long m = std::min<long>(check_every, max_iters - it);
-        for (long q = 0; q < m; ++q) {
-            e = launch_adjoint_step(c, nu[cur], nu[cur ^ 1], tr, acc, s);
+        // two iterations per launch where the check interval allows
+        for (long q = 0; q < m;) {
+            const bool two = c->pair && q + 1 < m;
+            e = two ? launch_adjoint_pair(c, nu[cur], nu[cur ^ 1], tr, tr, acc, s)
+                    : launch_adjoint_step(c, nu[cur], nu[cur ^ 1], tr, acc, s);
             if (e != hipSuccess) return hip_fail(c, e, "adjoint step");
             cur ^= 1;
+            q += two ? 2 : 1;
         }
         it += m;
         double nn = 0;

@@ -162,3 +162,28 @@ def test_steady_adjoint_matches_direct_steady_adjoint(real, tol):
     assert abs(eps / eps_ss - 1) < tol
     assert np.abs(grad - grad_ss).max() <= tol * np.abs(grad_ss).max()
     assert (grad[w.node_type < 2] == 0).all()
+
+
+@pytest.mark.parametrize("real,tol", [("f64", 1e-11), ("f32", 1e-4)])
+def test_steady_adjoint_two_step_equals_single_steps(real, tol):
+    # the steady iteration runs two adjoint steps per launch (an odd check
+    # interval ends each interval in a single step); flags bit 8 runs one per
+    # launch: same iteration count, gradients to round-off
+    w = make_workload("tiny")
+    out = []
+    for flags in (0, 256):
+        c = _ctx(w, real, flags=flags)
+        c.flow_init()
+        c.flow_run(3000)
+        c.adr_init()
+        c.adr_run(20000, tol=0)
+        eps, grad, iters = c.adjoint_steady(max_iters=200000, check_every=333,
+                                            tol=1e-12 if real == "f64" else 1e-6)
+        out.append((eps, grad.cpu().numpy(), iters))
+        c.close()
+    (e2, g2, i2), (e1, g1, i1) = out
+    assert i2 == i1
+    scale = np.abs(g1).max()
+    assert scale > 0
+    assert np.abs(g2 - g1).max() <= tol * scale
+    assert abs(e2 / e1 - 1) <= 1e-12
