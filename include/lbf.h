@@ -96,10 +96,11 @@ typedef struct {
                             node updates (default: 32-bit offsets through buffer
                             descriptors while the 9-plane flow lattice is below
                             4 GiB, 64-bit beyond; results are identical);
-                            bit 8: one ADR step per launch (default: untraced
-                            steps of a link-reaction channel run two per launch,
-                            the intermediate state kept in LDS; the last step of
-                            every block is a single one) */
+                            bit 8: one ADR step per launch (default: steps of a
+                            link-reaction channel run two per launch, the
+                            intermediate state kept in LDS; the last step of
+                            every block is a single one); the adjoint's steps
+                            likewise */
     int boundary;        /* 0: channel (solid rows 0 and ny-1, inlet at x = 0,
                             outlet at x = nx-1); 1: box periodic in x and y with no
                             inlet or outlet (ADR only: no flow solve, no fluxes,
