@@ -347,6 +347,50 @@ def no_flow_leg(steps=(10000, 50000, 100000)):
     return res
 
 
+def targets_leg(w, steps=2000):
+    """Throughput against 70 % of the 8 TB/s HBM peak (5.6 TB/s of algorithmic
+    bytes) for two more configurations of the same C2 lattice: the D2Q9 flow
+    with FP32 arithmetic (flags bit 5; 74 B per fluid node-step) and the ADR
+    with FP64 populations and two species (A -> B; 177 B per fluid node-step,
+    two steps per launch).  Random-init geometry and flow, short runs."""
+    import paper_2109_04455_amd as L
+    out = {}
+    nodes = w.nx * w.ny
+    target = 0.7 * PEAK_HBM_GBS
+    p = L.params(w.nx, w.ny, real="f32", nspecies=w.nspecies, tau_f=w.tau_f, u0=w.u0,
+                 tau_g=w.tau_g, c_in=w.c_in, vel_scale=w.vel_scale, flags=32)
+    c = L.Context(p)
+    c.set_geometry(w.node_type)
+    c.set_rates(w.k)
+    c.flow_init()
+    c.flow_run(200)
+    ms = min(c.time_flow_steps(1000) for _ in range(3)) / 1000
+    c.close()
+    fb = flow_bytes_per_step(w.node_type, 4)
+    out["flow_fp32_arithmetic"] = {
+        "mlups": round(nodes / (ms * 1e-3) / 1e6, 1), "us_per_step": round(ms * 1e3, 2),
+        "gbs": round(fb / (ms * 1e-3) / 1e9, 1), "frac": round(fb / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+        "target_mlups": round(target * 1e9 / (fb / nodes) / 1e6)}
+    p = L.params(w.nx, w.ny, real="f64", nspecies=2, tau_f=w.tau_f, u0=w.u0, tau_g=w.tau_g,
+                 c_in=w.c_in, vel_scale=w.vel_scale)
+    c = L.Context(p)
+    c.set_geometry(w.node_type)
+    c.set_rates(w.k)
+    c.flow_init()
+    c.flow_run(200)
+    c.adr_init()
+    c.adr_run(1001, tol=0)
+    ms = min(c.time_adr_steps(steps) for _ in range(2)) / steps
+    c.close()
+    ab, per_fluid = adr_bytes_per_step(w.node_type, 2, 8)
+    out["adr_fp64_two_species"] = {
+        "mlups": round(nodes / (ms * 1e-3) / 1e6, 1), "us_per_step": round(ms * 1e3, 2),
+        "bytes_per_fluid_node_step": per_fluid,
+        "gbs": round(ab / (ms * 1e-3) / 1e9, 1), "frac": round(ab / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+        "target_mlups": round(target * 1e9 / (ab / nodes) / 1e6)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -366,6 +410,7 @@ def main():
     ap.add_argument("--no-noflow", action="store_true")
     ap.add_argument("--no-rwpt", action="store_true")
     ap.add_argument("--no-c0", action="store_true")
+    ap.add_argument("--no-targets", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -476,6 +521,8 @@ def main():
         ux, uy = ctx.get_velocity()
         out["rwpt"] = rwpt_leg(w, ux, uy)
     ctx.close()
+    if not args.no_targets:
+        out["throughput_targets"] = targets_leg(w)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(args.adjoint_steps)
     if not args.no_batch:
