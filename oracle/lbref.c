@@ -387,6 +387,54 @@ void ref_adr_concentration(int nx, int ny, int ns, const uint8_t *type, const do
 }
 
 /* Total amount of each species over the fluid nodes (pre-collision). */
+/* Amount each reaction converts in the next step from the pre-collision
+ * state g (Eq. source_lbm summed over the lattice): rate[0] A -> B and, with
+ * three species, rate[1] B -> C.  Same reaction modes, rates and boundary
+ * wrapping as adr_step: the concentration is the fluid node's pre-collision
+ * one, summed over every reacting population. */
+void ref_adr_production(int nx, int ny, int ns, const uint8_t *type, const double *k,
+                        const double *k2, int mode, int bc, const double *g, double *rate)
+{
+    size_t n = (size_t)nx * ny;
+    rate[0] = rate[1] = 0.0;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            size_t id = (size_t)y * nx + x;
+            if (type[id] != 0) continue;
+            double c[3] = {0, 0, 0};
+            for (int s = 0; s < ns; ++s)
+                for (int i = 0; i < 5; ++i) c[s] += g[((size_t)s * 5 + i) * n + id];
+            if (mode == REF_LINK || mode == REF_NODE_AT_CATALYST) {
+                double ksum[2] = {0, 0};
+                int kcnt[2] = {0, 0};
+                for (int i = 1; i < 5; ++i) {
+                    int nxx = x + D5X[i], nyy = y + D5Y[i];
+                    if (bc & REF_PERIODIC_X) nxx = wrap(nxx, nx);
+                    if (bc & REF_PERIODIC_Y) nyy = wrap(nyy, ny);
+                    if (nxx < 0 || nxx >= nx || nyy < 0 || nyy >= ny) continue;
+                    size_t sid = (size_t)nyy * nx + nxx;
+                    int q = type[sid] == 2 ? 0 : (type[sid] == 3 && ns == 3 ? 1 : -1);
+                    if (q < 0) continue;
+                    if (mode == REF_LINK)
+                        rate[q] += k[sid] * d5w(i) * c[q];
+                    else {
+                        ksum[q] += k[sid];
+                        kcnt[q]++;
+                    }
+                }
+                if (mode == REF_NODE_AT_CATALYST)
+                    for (int q = 0; q < 2; ++q)
+                        if (kcnt[q])
+                            for (int i = 0; i < 5; ++i) rate[q] += ksum[q] / kcnt[q] * d5w(i) * c[q];
+            } else {
+                for (int i = 0; i < 5; ++i) {
+                    rate[0] += k[id] * d5w(i) * c[0];
+                    if (ns == 3 && k2) rate[1] += k2[id] * d5w(i) * c[1];
+                }
+            }
+        }
+}
+
 void ref_adr_totals(int nx, int ny, int ns, const uint8_t *type, const double *g, double *tot)
 {
     size_t n = (size_t)nx * ny;

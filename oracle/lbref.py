@@ -61,6 +61,7 @@ def lib():
         _lib.ref_adr_observe.argtypes = [i, i, i, p, p, d, i, p, p]
         _lib.ref_adr_concentration.argtypes = [i, i, i, p, p, p]
         _lib.ref_adr_totals.argtypes = [i, i, i, p, p, p]
+        _lib.ref_adr_production.argtypes = [i, i, i, p, p, p, i, i, p, p]
     return _lib
 
 
@@ -207,3 +208,18 @@ def adr_totals(node_type, g):
     tot = np.zeros(ns)
     lib().ref_adr_totals(nx, ny, ns, _ptr(t), _ptr(g), _ptr(tot))
     return tot
+
+
+def adr_production(node_type, k, g, mode=LINK, bc=0, k2=None):
+    """Amount each reaction converts in the next step from the pre-collision
+    state g (Eq. source_lbm summed over the lattice): [A->B] or, with three
+    species, [A->B, B->C]."""
+    t = _u8(node_type)
+    ny, nx = t.shape
+    ns = g.shape[0]
+    assert g.flags.c_contiguous and g.dtype == np.float64 and g.shape == (ns, 5, ny, nx)
+    k = _f64(k)
+    k2 = None if k2 is None else _f64(k2)
+    rate = np.zeros(2)
+    lib().ref_adr_production(nx, ny, ns, _ptr(t), _ptr(k), _ptr(k2), mode, bc, _ptr(g), _ptr(rate))
+    return rate[: ns - 1]

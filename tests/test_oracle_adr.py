@@ -361,3 +361,48 @@ def test_all_populations_variant_equals_node_reaction_with_neighbour_mean_rates(
     tot = R.adr_totals(t, ga)
     assert abs(tot.sum() - (t == 0).sum()) < 1e-9   # closed box: A + B + C conserved
     assert tot[2] > 0
+
+
+def test_production_of_the_uniform_state_has_its_closed_form():
+    # closed box at rest, uniform A = 1: the link reaction converts sum over
+    # links of k w_i, the all-populations variant k at every fluid node next
+    # to a type-1 catalyst (brute force over the lattice)
+    t, k, surf = _closed_box_disc()
+    ny, nx = t.shape
+    g = np.zeros((2, 5, ny, nx))
+    g[0] = np.where(t == 0, _eq_state(np.ones((ny, nx)), 0, 0)[0], 0.0)
+    links = reactive = 0
+    for y in range(ny):
+        for x in range(nx):
+            if t[y, x] != 0:
+                continue
+            n = sum(t[(y + CY[i]) % ny, (x + CX[i]) % nx] == CAT1 for i in range(1, 5))
+            links += n
+            reactive += n > 0
+    bc = R.PERIODIC_X | R.PERIODIC_Y
+    assert links > 0
+    assert abs(R.adr_production(t, k, g, R.LINK, bc)[0] - 0.3 * links / 6) < 1e-13
+    assert abs(R.adr_production(t, k, g, R.NODE_AT_CATALYST, bc)[0] - 0.3 * reactive) < 1e-13
+
+
+@pytest.mark.parametrize("mode", [R.LINK, R.NODE_AT_CATALYST])
+def test_production_is_the_change_of_the_totals_in_a_closed_box(mode):
+    # in a closed box (periodic, inert walls, no flow) one step changes the
+    # totals by the reaction amounts only: A by -r0, B by r0 - r1, C by r1
+    from workloads.configs import box_workload
+    w = box_workload("side", n=60, da=40.0)
+    t = w.node_type
+    ny, nx = t.shape
+    z = np.zeros((ny, nx))
+    bc = R.PERIODIC_X | R.PERIODIC_Y
+    g = R.adr_init(t, z, z, 3)
+    R.adr_run(t, w.k, z, z, g, w.tau_g, 300, mode=mode, bc=bc)
+    r = R.adr_production(t, w.k, g, mode, bc)
+    before = R.adr_totals(t, g)
+    R.adr_run(t, w.k, z, z, g, w.tau_g, 1, mode=mode, bc=bc)
+    d = R.adr_totals(t, g) - before
+    assert r[0] > 0 and r[1] > 0
+    scale = before.sum()
+    assert abs(d[0] + r[0]) < 1e-12 * scale
+    assert abs(d[1] - (r[0] - r[1])) < 1e-12 * scale
+    assert abs(d[2] - r[1]) < 1e-12 * scale
