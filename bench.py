@@ -318,7 +318,8 @@ def rwpt_leg(w, ux, uy, steps=200, density=10.0):
 def no_flow_leg(steps=(10000, 50000, 100000)):
     """The paper's pure-diffusion cascade (300x300 periodic box, Da 150, no
     flow): total C over time for two fibres 100 apart vs one side-by-side
-    fibre of the same catalytic surface."""
+    fibre of the same catalytic surface, and the production of C per step
+    (B -> C conversion) at the same times."""
     import torch
     import paper_2109_04455_amd as L
     from workloads import box_workload
@@ -333,14 +334,16 @@ def no_flow_leg(steps=(10000, 50000, 100000)):
         z = torch.zeros((w.ny, w.nx), dtype=torch.float32)
         c.set_velocity(z, z)
         c.adr_init()
-        done, series = 0, []
+        done, series, prod = 0, [], []
         t0 = time.perf_counter()
         for s in steps:
             c.adr_run(s - done, check_every=s - done, tol=0)
             done = s
             tot = c.totals()
             series.append([s, float(tot[2] / tot.sum())])
-        res[morph] = {"C_fraction": series, "seconds": round(time.perf_counter() - t0, 3)}
+            prod.append([s, float(c.production()[1] / tot.sum())])
+        res[morph] = {"C_fraction": series, "C_production_per_step": prod,
+                      "seconds": round(time.perf_counter() - t0, 3)}
         c.close()
     res["side_by_side_faster"] = all(b[1] > a[1] for a, b in zip(res["pair"]["C_fraction"],
                                                                   res["side"]["C_fraction"]))

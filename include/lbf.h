@@ -176,6 +176,17 @@ lbf_status lbf_get_concentration(lbf_ctx ctx, int species, void *out_dev);
  * conversion of the time-dependent problem.  Requires at least one step
  * (LBF_ESTATE).  Synchronises. */
 lbf_status lbf_adr_totals(lbf_ctx ctx, double *totals);
+/* Production of the reactions: the amount each converts in the next step
+ * from the current state (the source term of Eq. source_lbm summed over the
+ * lattice, FP64, fixed summation order), rates[0] for A -> B and, with three
+ * species, rates[1] for B -> C (host double, nspecies - 1 values).  Link
+ * reactions take k of the catalytic node times w_i times the fluid node's
+ * concentration per link; the all-populations variant the mean neighbour
+ * rate times the concentration per reacting node.  In a periodic box with
+ * inert walls, the next step changes the totals of A, B, C by exactly
+ * -rates[0], rates[0] - rates[1], rates[1] (up to rounding).  Requires at
+ * least one step (LBF_ESTATE).  Synchronises. */
+lbf_status lbf_adr_production(lbf_ctx ctx, double *rates);
 /* Number of ADR steps taken since lbf_adr_init. */
 lbf_status lbf_adr_steps(lbf_ctx ctx, long *steps);
 

@@ -200,6 +200,13 @@ class Context:
         self._call("lbf_adr_totals", t)
         return np.array(t[: self.ns])
 
+    def production(self):
+        """Amount each reaction converts in the next step: [A->B] or
+        [A->B, B->C] (FP64 sums over the lattice)."""
+        r = (ctypes.c_double * 2)()
+        self._call("lbf_adr_production", r)
+        return np.array(r[: self.ns - 1])
+
     def adr_steps(self):
         s = ctypes.c_long()
         self._call("lbf_adr_steps", ctypes.byref(s))

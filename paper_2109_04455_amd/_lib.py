@@ -72,6 +72,7 @@ SIGNATURES = {
     "lbf_efficiency": (_I, [_P, _PD, _PD, _PD]),
     "lbf_get_concentration": (_I, [_P, _I, _P]),
     "lbf_adr_totals": (_I, [_P, _PD]),
+    "lbf_adr_production": (_I, [_P, _PD]),
     "lbf_adr_steps": (_I, [_P, _PL]),
     "lbf_adjoint_workspace_bytes": (_I, [_P, _L, _I, _I, _PS]),
     "lbf_adr_adjoint": (_I, [_P, _L, _I, _I, _P, _S, _PD, _P]),

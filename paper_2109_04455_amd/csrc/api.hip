@@ -654,6 +654,22 @@ lbf_status lbf_adr_totals(lbf_ctx c, double *totals)
     return read_obs(c, totals, c->p.nspecies);
 }
 
+lbf_status lbf_adr_production(lbf_ctx c, double *rates)
+{
+    lbf_status st = check_ready(c, true);
+    if (st != LBF_OK) return st;
+    if (!rates) return fail(c, LBF_EINVAL, "NULL output");
+    if (c->adr_steps < 1) return fail(c, LBF_ESTATE, "no ADR step taken yet");
+    const int prev = c->gpar ^ 1;
+    constexpr int NB = 256;  // blocks; 2 x NB partials fit the workspace partial block
+    double *partial = (double *)c->ptr(c->off.partial);
+    double *obs = (double *)c->ptr(c->off.obs);
+    hipError_t e = launch_production(c->p.real_bytes, c->p.nspecies, adr_args<float>(c, prev),
+                                     adr_args<double>(c, prev), partial, NB, obs, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "production kernel");
+    return read_obs(c, rates, c->p.nspecies - 1);
+}
+
 lbf_status lbf_adr_steps(lbf_ctx c, long *steps)
 {
     if (!c || !steps) return LBF_EINVAL;

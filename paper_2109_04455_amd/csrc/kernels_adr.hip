@@ -302,6 +302,75 @@ __global__ __launch_bounds__(256) void k_totals(AdrArgs<Real> a, double *partial
         for (int s = 0; s < S; ++s) partial[(size_t)s * gridDim.x + blockIdx.x] = sm[s][0];
 }
 
+// Amount each reaction converts in the step from the state `a.src` streams
+// into (Eq. source_lbm summed over the lattice, FP64): partial[q] sums
+// A -> B (q = 0) and B -> C (q = 1) per block, fixed reduction order.  The
+// concentration of a node is its pulled pre-collision one; link reactions
+// take the rate of the catalytic node, the all-populations variant the mean
+// rate of the node's catalytic neighbours of the type.
+template <typename Real, int S>
+__global__ __launch_bounds__(256) void k_production(AdrArgs<Real> a, double *partial)
+{
+    __shared__ double sm[2][256];
+    double acc[2] = {0.0, 0.0};
+    const size_t n = (size_t)a.nx * a.ny;
+    const double inlet_e = 2.0 * w5<double>(DE) * (a.cin - a.cref);
+    const int off[5] = {0, 1, a.nxp, -1, -a.nxp};
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % a.nx), y = (int)(i / a.nx);
+        const size_t id = (size_t)y * a.nxp + x;
+        const unsigned m = a.mask5[id];
+        if (m == MASK5_SOLID || !(m & 0xF0u)) continue;
+        size_t nb[5];
+        if (a.L.periodic) periodic_neighbours(x, y, a.nx, a.ny, a.nxp, nb);
+        double c[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            double h[5];
+            if (a.L.periodic)
+                pull5_periodic<Real, double, false>(a.src + (size_t)s * 5 * a.plane, a.plane, id, nb, m, h);
+            else
+                pull5<Real, double, false, true>(a.src + (size_t)s * 5 * a.plane, a.plane, id, x, a.nx,
+                                                 a.nxp, m, s == 0, inlet_e, h);
+            c[s] = (s == 0 ? a.cref : 0.0) + (h[0] + h[1] + h[2] + h[3] + h[4]);
+        }
+        double ks[2] = {0.0, 0.0};
+        int kc[2] = {0, 0};
+#pragma unroll
+        for (int d = 1; d < 5; ++d) {
+            if (!((m >> (3 + d)) & 1u)) continue;
+            const size_t sid = a.L.periodic ? nb[d] : id + off[d];
+            const int q = a.type[sid] == 2 ? 0 : 1;
+            if (q == 1 && S == 2) continue;
+            if (a.L.mode == 0) {
+                acc[q] += (double)a.kr[sid] * w5<double>(d) * c[q];
+            } else {
+                ks[q] += (double)a.kr[sid];
+                kc[q] += 1;
+            }
+        }
+        if (a.L.mode != 0)
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+                if (kc[q]) acc[q] += ks[q] / kc[q] * c[q];
+    }
+    sm[0][threadIdx.x] = acc[0];
+    sm[1][threadIdx.x] = acc[1];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            sm[0][threadIdx.x] += sm[0][threadIdx.x + st];
+            sm[1][threadIdx.x] += sm[1][threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = sm[0][0];
+        partial[gridDim.x + blockIdx.x] = sm[1][0];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_sum_partials(const double *partial, int nblocks, int ns,
                                                       double *out)
 {
@@ -528,6 +597,22 @@ hipError_t launch_totals(int real_bytes, int ns, const AdrArgs<float> &af, const
         else hipLaunchKernelGGL((k_totals<double, 3>), g, b, 0, s, ad, partial);
     }
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partial, nblocks, ns, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_production(int real_bytes, int ns, const AdrArgs<float> &af,
+                             const AdrArgs<double> &ad, double *partial, int nblocks, double *out,
+                             hipStream_t s)
+{
+    const dim3 g(nblocks), b(256);
+    if (real_bytes == 4) {
+        if (ns == 2) hipLaunchKernelGGL((k_production<float, 2>), g, b, 0, s, af, partial);
+        else hipLaunchKernelGGL((k_production<float, 3>), g, b, 0, s, af, partial);
+    } else {
+        if (ns == 2) hipLaunchKernelGGL((k_production<double, 2>), g, b, 0, s, ad, partial);
+        else hipLaunchKernelGGL((k_production<double, 3>), g, b, 0, s, ad, partial);
+    }
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partial, nblocks, 2, out);
     return hipGetLastError();
 }
 

@@ -88,6 +88,9 @@ struct AdrArgs {
 // launchers (return hipError_t of the launch)
 hipError_t launch_masks(const uint8_t *type_in, uint8_t *type_pad, uint8_t *mask5, uint16_t *mask9,
                         int nx, int ny, int nxp, int nspecies, bool periodic, hipStream_t s);
+hipError_t launch_production(int real_bytes, int ns, const AdrArgs<float> &af,
+                             const AdrArgs<double> &ad, double *partial, int nblocks, double *out,
+                             hipStream_t s);
 hipError_t launch_totals(int real_bytes, int ns, const AdrArgs<float> &af, const AdrArgs<double> &ad,
                          double *partial, int nblocks, double *out, hipStream_t s);
 hipError_t launch_trace_list(const uint8_t *mask5, int32_t *trace_idx, int32_t *trace_nodes,

@@ -148,6 +148,49 @@ def test_totals_match_oracle_in_channel():
     c.close()
 
 
+@pytest.mark.parametrize("real", ["f64", "f32"])
+@pytest.mark.parametrize("case,mode", [("box", 0), ("box", 1), ("channel", 0), ("channel", 1)])
+def test_production_matches_oracle(real, case, mode):
+    # reaction production after n steps against the oracle's from its state
+    # after n steps: 130 x 130 side-by-side box and the 64 x 32 cascade
+    # channel with its flow, both reaction forms
+    if case == "box":
+        w = box_workload("side", real=real, n=130, xi=40)
+        ux = uy = np.zeros((w.ny, w.nx))
+    else:
+        w = make_workload("tiny")
+        ux, uy, _, _ = R.flow_steady(w.node_type, w.tau_f, w.u0, 3000, tol=0)
+        ux, uy = _rounded(ux, real), _rounded(uy, real)
+    steps = 600
+    print(f"production {case} mode {mode} {real}", flush=True)
+    c, _, _ = _gpu_adr(w, real, mode, ux, uy, steps)
+    r = c.production()
+    c.close()
+    g, _, _ = _oracle_adr(w, mode, ux, uy, steps)
+    bc = (R.PERIODIC_X | R.PERIODIC_Y) if w.boundary == 1 else 0
+    ro = R.adr_production(w.node_type, w.k, g, R.NODE_AT_CATALYST if mode == 1 else R.LINK, bc)
+    assert r.shape == ro.shape == (w.nspecies - 1,)
+    assert (ro > 0).all()
+    assert np.abs(r - ro).max() <= TOL[real] * ro.max()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_production_is_the_change_of_the_totals_in_a_closed_box(mode):
+    # one GPU step changes the totals of A, B, C by -r0, r0 - r1, r1
+    w = box_workload("side", real="f64", n=130, xi=40)
+    z = np.zeros((w.ny, w.nx))
+    c, _, before = _gpu_adr(w, "f64", mode, z, z, 500)
+    r = c.production()
+    c.adr_run(1, check_every=1, tol=0)
+    d = c.totals() - before
+    c.close()
+    scale = before.sum()
+    assert r[0] > 0 and r[1] > 0
+    assert abs(d[0] + r[0]) <= 1e-12 * scale
+    assert abs(d[1] - (r[0] - r[1])) <= 1e-12 * scale
+    assert abs(d[2] - r[1]) <= 1e-12 * scale
+
+
 def test_periodic_box_rejects_channel_only_calls():
     L = _lbf()
     w = box_workload("pair", real="f64", n=64, xi=20)
