@@ -15,7 +15,10 @@ DEFAULT_CANDIDATES = (
     # shape then apply to the single steps that end each block); flags bit 8
     # (256): one step per launch; bit 1 (2): cached instead of streaming.
     (1, 256, 1, 0), (1, 256, 1, 2),
-    (1, 256, 1, 256), (1, 512, 1, 256), (1, 128, 2, 256), (1, 64, 4, 256), (1, 1024, 1, 256),
+    (1, 256, 1, 256), (1, 512, 1, 256), (1, 1024, 1, 256),
+    (1, 64, 1, 256), (1, 64, 2, 256), (1, 64, 4, 256), (1, 64, 8, 256),
+    (1, 128, 1, 256), (1, 128, 2, 256), (1, 128, 4, 256), (1, 128, 8, 256),
+    (1, 256, 2, 256), (1, 256, 4, 256),
     (2, 64, 4, 256), (2, 64, 1, 256), (2, 128, 2, 256),
     (1, 256, 1, 256 | 2),
 )
