@@ -418,8 +418,10 @@ __global__ void k_step_begin(Scalars *sc, long long buf_count, long long capacit
 // per block and species.  Particles below this step's insertion point
 // (n_alive) that are no longer alive left the domain since the last
 // compaction and stay where they are until the next one removes them; the
-// particles moved are counted (n_held).
-__global__ __launch_bounds__(256) void k_move(Field f, Parts p, Scalars *sc, double plane,
+// particles moved are counted (n_held).  At most 96 VGPRs (five wavefronts
+// per SIMD, two registers spilled) hide more of the gathers' latency than 101
+// VGPRs and four wavefronts; six wavefronts spill 17 and run slower.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_move(Field f, Parts p, Scalars *sc, double plane,
                                               int measure)
 {
     __shared__ long long cnt[4];
