@@ -29,6 +29,7 @@ struct Inst {
     FlowArgs<Real> flow;
     int tiles_x, tiles_y;    // tile grid of this instance (one-step kernels)
     int ptiles_x, ptiles_y;  // tile grid of the two-step kernel
+    int ftiles_y;            // tile rows of the flow (two lattice rows per thread)
     int xf;
     double cin, cref;
 };
@@ -95,6 +96,8 @@ template <typename Real, bool WRITE_U, bool NT, bool WIDE, bool PERSIST>
 __global__ __launch_bounds__(256) void k_batch_flow(const Inst<Real> *insts, const int4 *tiles,
                                                     const int *ntiles, int parity, int tx, int ty)
 {
+    // a flow tile is tx x 2 ty nodes: thread row j takes lattice rows 2j and
+    // 2j + 1 of the tile (FP64 arithmetic, as the single-lattice flow)
     int t0, t1;
     if (PERSIST) {
         chunk_of_block(*ntiles, t0, t1);
@@ -112,21 +115,21 @@ __global__ __launch_bounds__(256) void k_batch_flow(const Inst<Real> *insts, con
             a.dst = const_cast<Real *>(tmp);
         }
         const int x = T.y * tx + (int)threadIdx.x % tx;
-        const int y = T.z * ty + (int)threadIdx.x / tx;
-        if (x < a.nx && y < a.ny) flow::node_update<Real, double, WRITE_U, NT, WIDE>(a, x, y);
+        const int y = T.z * 2 * ty + 2 * ((int)threadIdx.x / tx);
+        if (x < a.nx && y < a.ny) flow::node_update2<Real, double, WRITE_U, NT, WIDE>(a, x, y);
     }
 }
 
-// Rebuild a tile table from the per-instance active flags (one block): the
-// one-step tiles, or with `pair` the tiles of the two-step kernel.
+// Rebuild a tile table from the per-instance active flags (one block): kind
+// 0 the one-step tiles, 1 the tiles of the two-step kernel, 2 the flow tiles.
 template <typename Real>
-__global__ void k_build_tiles(const Inst<Real> *insts, const int *active, int n, bool pair,
+__global__ void k_build_tiles(const Inst<Real> *insts, const int *active, int n, int kind,
                               int4 *tiles, int *ntiles)
 {
     __shared__ int base[1025];
     auto grid_of = [&](int i, int &gx, int &gy) {
-        gx = pair ? insts[i].ptiles_x : insts[i].tiles_x;
-        gy = pair ? insts[i].ptiles_y : insts[i].tiles_y;
+        gx = kind == 1 ? insts[i].ptiles_x : insts[i].tiles_x;
+        gy = kind == 1 ? insts[i].ptiles_y : (kind == 2 ? insts[i].ftiles_y : insts[i].tiles_y);
     };
     if (threadIdx.x == 0) {
         int acc = 0;
@@ -282,6 +285,7 @@ void fill_insts(lbf_batch b, std::vector<Inst<Real>> &v)
         I.flow = flow_args<Real>(c, 0);
         I.tiles_x = (c->p.nx + b->tx - 1) / b->tx;
         I.tiles_y = (c->p.ny + b->ty - 1) / b->ty;
+        I.ftiles_y = (c->p.ny + 2 * b->ty - 1) / (2 * b->ty);
         int ptx, pty;
         pair_tile(c->p.real_bytes, ptx, pty);
         I.ptiles_x = (c->p.nx + ptx - 1) / ptx;
@@ -311,7 +315,10 @@ hipError_t upload_insts(lbf_batch b)
     return e;
 }
 
-hipError_t set_active(lbf_batch b, const std::vector<int> &act)
+// Upload the active flags and rebuild the tile tables: the two-step table,
+// and in the one-step slot the one-step tiles or, for the flow phase, the
+// flow tiles.
+hipError_t set_active(lbf_batch b, const std::vector<int> &act, bool flow = false)
 {
     hipError_t e = hipMemcpyAsync(b->ws + b->off_active, act.data(), act.size() * sizeof(int),
                                   hipMemcpyHostToDevice, b->stream);
@@ -320,13 +327,14 @@ hipError_t set_active(lbf_batch b, const std::vector<int> &act)
         int4 *tiles = (int4 *)(b->ws + (pair ? b->off_ptiles : b->off_tiles));
         int *nt = (int *)(b->ws + (pair ? b->off_nptiles : b->off_ntiles));
         const int *act_d = (const int *)(b->ws + b->off_active);
+        const int kind = pair ? 1 : (flow ? 2 : 0);
         if (b->p[0].real_bytes == 4)
             hipLaunchKernelGGL(k_build_tiles<float>, dim3(1), dim3(256), 0, b->stream,
-                               (const Inst<float> *)(b->ws + b->off_inst), act_d, b->n, pair != 0,
+                               (const Inst<float> *)(b->ws + b->off_inst), act_d, b->n, kind,
                                tiles, nt);
         else
             hipLaunchKernelGGL(k_build_tiles<double>, dim3(1), dim3(256), 0, b->stream,
-                               (const Inst<double> *)(b->ws + b->off_inst), act_d, b->n, pair != 0,
+                               (const Inst<double> *)(b->ws + b->off_inst), act_d, b->n, kind,
                                tiles, nt);
         e = hipGetLastError();
     }
@@ -651,7 +659,7 @@ lbf_status lbf_batch_flow(lbf_batch b, long max_steps, int check_every, double t
     }
     b->fpar = 0;
     std::vector<int> act(b->n, 1);
-    hipError_t e = set_active(b, act);
+    hipError_t e = set_active(b, act, true);
     if (e != hipSuccess) return bhip(b, e, "tile table");
     long steps = 0;
     int nact = b->n;
@@ -691,7 +699,7 @@ lbf_status lbf_batch_flow(lbf_batch b, long max_steps, int check_every, double t
                 }
             }
             if (changed) {
-                e = set_active(b, act);
+                e = set_active(b, act, true);
                 if (e != hipSuccess) return bhip(b, e, "tile table");
             }
         }

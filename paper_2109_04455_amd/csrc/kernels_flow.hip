@@ -28,9 +28,34 @@ __global__ __launch_bounds__(1024) void k_flow_step(FlowArgs<Real> a)
     flow::node_update<Real, Acc, WRITE_U, NT, WIDE>(a, x, y);
 }
 
+// Two rows per thread (FP64 arithmetic): the launch covers ceil(ny / 2)
+// tile rows, thread row y taking lattice rows 2y and 2y + 1.
+template <typename Real, typename Acc, bool WRITE_U, bool NT, bool WIDE>
+__global__ __launch_bounds__(1024) void k_flow_step2r(FlowArgs<Real> a)
+{
+    int x, y;
+    tile_coords(a.L, x, y);
+    y *= 2;
+    if (x >= a.nx || y >= a.ny) return;
+    flow::node_update2<Real, Acc, WRITE_U, NT, WIDE>(a, x, y);
+}
+
 template <typename Real, typename Acc, bool WIDE>
 void flow_launch_w(bool write_u, const FlowArgs<Real> &a, hipStream_t s)
 {
+    if constexpr (sizeof(Acc) == 8) {
+        FlowArgs<Real> a2 = a;
+        a2.L.gy = ((a.ny + 1) / 2 + a.L.ty - 1) / a.L.ty;
+        const dim3 g = a2.L.grid(), b = a2.L.block();
+        if (a.L.nontemporal) {
+            if (write_u) hipLaunchKernelGGL((k_flow_step2r<Real, Acc, true, true, WIDE>), g, b, 0, s, a2);
+            else hipLaunchKernelGGL((k_flow_step2r<Real, Acc, false, true, WIDE>), g, b, 0, s, a2);
+        } else {
+            if (write_u) hipLaunchKernelGGL((k_flow_step2r<Real, Acc, true, false, WIDE>), g, b, 0, s, a2);
+            else hipLaunchKernelGGL((k_flow_step2r<Real, Acc, false, false, WIDE>), g, b, 0, s, a2);
+        }
+        return;
+    }
     const dim3 g = a.L.grid(), b = a.L.block();
     if (a.L.nontemporal) {
         if (write_u)
