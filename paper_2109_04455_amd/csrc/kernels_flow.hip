@@ -40,10 +40,14 @@ __global__ __launch_bounds__(1024) void k_flow_step2r(FlowArgs<Real> a)
     flow::node_update2<Real, Acc, WRITE_U, NT, WIDE>(a, x, y);
 }
 
+// Lattices below this many nodes (launch-bound: a few blocks per step) keep
+// one row per thread.
+constexpr long FLOW_TWO_ROWS_MIN_NODES = 1L << 18;
+
 template <typename Real, typename Acc, bool WIDE>
 void flow_launch_w(bool write_u, const FlowArgs<Real> &a, hipStream_t s)
 {
-    if constexpr (sizeof(Acc) == 8) {
+    if (sizeof(Acc) == 8 && (long)a.nx * a.ny >= FLOW_TWO_ROWS_MIN_NODES) {
         FlowArgs<Real> a2 = a;
         a2.L.gy = ((a.ny + 1) / 2 + a.L.ty - 1) / a.L.ty;
         const dim3 g = a2.L.grid(), b = a2.L.block();
