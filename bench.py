@@ -192,7 +192,60 @@ def precision_leg(steps=20000, flow_steps=5000):
             "field_rel_err": field}
 
 
-def batch_leg(steps=2000, flow_steps=2000):
+_ORACLE_INSTANCE = """
+import json, sys, time
+sys.path.insert(0, sys.argv[1])
+from oracle import lbref as R
+from workloads import batch_instances
+i, steps, flow_steps = int(sys.argv[2]), int(sys.argv[3]), int(sys.argv[4])
+w = batch_instances()[i]
+ux, uy, _, _ = R.flow_steady(w.node_type, w.tau_f, w.u0, flow_steps, tol=0)
+g = R.adr_init(w.node_type, ux, uy, w.nspecies, w.c_in, w.vel_scale)
+t0 = time.perf_counter()
+R.adr_run(w.node_type, w.k, ux, uy, g, w.tau_g, steps, w.c_in, w.vel_scale)
+print(json.dumps([w.node_type.size * steps, time.perf_counter() - t0]))
+"""
+
+
+def cpu_sweep_baseline(nproc=8, steps=20, flow_steps=5, timeout=300):
+    """The oracle on the first nproc sweep instances at once, one
+    single-threaded process per instance and core (child interpreters that
+    never touch the GPU): aggregate MLUPS = all node-steps over the longest
+    process's ADR time.  None if a child fails."""
+    import subprocess
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    nproc = max(1, min(nproc, ncpu, 16))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    procs = [subprocess.Popen([sys.executable, "-c", _ORACLE_INSTANCE, ROOT, str(i), str(steps),
+                               str(flow_steps)], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL,
+                              env=env) for i in range(nproc)]
+    res = []
+    try:
+        for p in procs:
+            out, _ = p.communicate(timeout=timeout)
+            if p.returncode != 0:
+                return None
+            res.append(json.loads(out.decode().strip().splitlines()[-1]))
+    except (subprocess.TimeoutExpired, ValueError, IndexError):
+        return None
+    finally:
+        for p in procs:
+            if p.poll() is None:
+                p.kill()
+                p.wait()
+    work = sum(r[0] for r in res)
+    longest = max(r[1] for r in res)
+    return {"value": round(work / longest / 1e6, 2), "unit": "MLUPS", "processes": nproc,
+            "kind": "oracle",
+            "sample": f"first {nproc} sweep instances, {steps} ADR steps each after {flow_steps} "
+                      f"flow steps, one single-threaded FP64 oracle process per instance, run at "
+                      f"once ({longest:.1f} s)"}
+
+
+def batch_leg(steps=2000, flow_steps=2000, cpu=True):
     """The 64-instance Pe x Da sweep for a fixed number of steps: one batched
     launch per step (tile shape and launch mode chosen by the autotuner) vs
     the same instances run one after another through the single-lattice path
@@ -220,7 +273,8 @@ def batch_leg(steps=2000, flow_steps=2000):
             "batched_flow_s": round(b["flow_seconds"], 3), "serial_flow_s": round(s["flow_seconds"], 3),
             "batched_setup_s": round(b["setup_seconds"], 3),
             "serial_setup_s": round(s["setup_seconds"], 3),
-            "identical_results": same}
+            "identical_results": same,
+            "cpu_oracle": cpu_sweep_baseline() if cpu else None}
 
 def membrane3d_leg(steps=2000):
     """3D randomly oriented fibre membranes (D3Q19 forced flow, D3Q7 ADR, FP32
@@ -529,7 +583,7 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(args.adjoint_steps)
     if not args.no_batch:
-        out["batched_sweep"] = batch_leg(args.batch_steps)
+        out["batched_sweep"] = batch_leg(args.batch_steps, cpu=not args.no_cpu_baseline)
     if not args.no_precision:
         out["fp32_vs_fp64"] = precision_leg()
     if not args.no_3d:
