@@ -245,7 +245,7 @@ def cpu_sweep_baseline(nproc=8, steps=20, flow_steps=5, timeout=300):
                       f"once ({longest:.1f} s)"}
 
 
-def batch_leg(steps=2000, flow_steps=2000, cpu=True):
+def batch_leg(steps=2000, flow_steps=2000, cpu=True, tts_steps=0, tts_tol=1e-6):
     """The 64-instance Pe x Da sweep for a fixed number of steps: one batched
     launch per step (tile shape and launch mode chosen by the autotuner) vs
     the same instances run one after another through the single-lattice path
@@ -260,6 +260,19 @@ def batch_leg(steps=2000, flow_steps=2000, cpu=True):
     b = sweep_batched(ws, flow_steps, steps, check_every=1000, tile=tile, flags=flags)
     s = sweep_serial(ws, flow_steps, steps, check_every=1000)
     same = bool((b["product_flux"] == s["product_flux"]).all())
+    tts = None
+    if tts_steps > 0:
+        # time to solution: every instance runs until eps changes by less than
+        # tts_tol of itself over 1000 steps, or tts_steps (converged instances
+        # leave the batched launch; the serial path stops each on its own)
+        bt = sweep_batched(ws, flow_steps, tts_steps, check_every=1000, tol=tts_tol, tile=tile,
+                           flags=flags)
+        st = sweep_serial(ws, flow_steps, tts_steps, check_every=1000, tol=tts_tol)
+        tts = {"max_steps": tts_steps, "tol": tts_tol,
+               "batched_s": round(bt["seconds"], 2), "serial_s": round(st["seconds"], 2),
+               "speedup": round(st["seconds"] / bt["seconds"], 3),
+               "converged": int((bt["steps"] < tts_steps).sum()),
+               "same_steps": bool((bt["steps"] == st["steps"]).all())}
     return {"instances": len(ws), "nodes": nodes, "steps": steps,
             "autotuned": {"tile": list(tile), "mode": ("one block per tile" if flags & 8 else
                                                     "persistent tile walk") +
@@ -274,7 +287,8 @@ def batch_leg(steps=2000, flow_steps=2000, cpu=True):
             "batched_setup_s": round(b["setup_seconds"], 3),
             "serial_setup_s": round(s["setup_seconds"], 3),
             "identical_results": same,
-            "cpu_oracle": cpu_sweep_baseline() if cpu else None}
+            "cpu_oracle": cpu_sweep_baseline() if cpu else None,
+            "time_to_solution": tts}
 
 def membrane3d_leg(steps=2000):
     """3D randomly oriented fibre membranes (D3Q19 forced flow, D3Q7 ADR, FP32
@@ -462,6 +476,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=20000)
     ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--batch-tts-steps", type=int, default=0,
+                    help="also time the sweep to convergence, capped at this many ADR steps")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--no-noflow", action="store_true")
@@ -583,7 +599,8 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(args.adjoint_steps)
     if not args.no_batch:
-        out["batched_sweep"] = batch_leg(args.batch_steps, cpu=not args.no_cpu_baseline)
+        out["batched_sweep"] = batch_leg(args.batch_steps, cpu=not args.no_cpu_baseline,
+                                         tts_steps=args.batch_tts_steps)
     if not args.no_precision:
         out["fp32_vs_fp64"] = precision_leg()
     if not args.no_3d:
