@@ -423,7 +423,8 @@ def targets_leg(w, steps=2000):
     bytes) for two more configurations of the same C2 lattice: the D2Q9 flow
     with FP32 arithmetic (flags bit 5; 74 B per fluid node-step) and the ADR
     with FP64 populations and two species (A -> B; 177 B per fluid node-step,
-    two steps per launch).  Random-init geometry and flow, short runs."""
+    two steps per launch).  The C2 geometry, 200 flow steps from the initial
+    state, then timed steps."""
     import paper_2109_04455_amd as L
     out = {}
     nodes = w.nx * w.ny
