@@ -191,6 +191,30 @@ def test_production_is_the_change_of_the_totals_in_a_closed_box(mode):
     assert abs(d[2] - r[1]) <= 1e-12 * scale
 
 
+def test_production_equals_the_product_outflow_at_steady_state():
+    # C0 run to a tight steady state: the A -> B conversion per step equals
+    # the B leaving through the outlet face (the paper's production rate),
+    # and the inflow minus it the A leaving
+    L = _lbf()
+    w = make_workload("C0")
+    p = L.params(w.nx, w.ny, real="f64", nspecies=w.nspecies, tau_f=w.tau_f, u0=w.u0,
+                 tau_g=w.tau_g, c_in=w.c_in, vel_scale=w.vel_scale)
+    c = L.Context(p)
+    c.set_geometry(w.node_type)
+    c.set_rates(w.k)
+    c.flow_init()
+    c.flow_run(10000)
+    c.adr_init()
+    steps, conv = c.adr_run(400000, check_every=1000, tol=1e-11)
+    eps, N, inflow = c.efficiency()
+    r = c.production()
+    c.close()
+    print("C0 steady", steps, conv, r, N, inflow, flush=True)
+    assert conv and r.shape == (1,)
+    assert abs(r[0] - N[1]) <= 1e-7 * inflow
+    assert abs(inflow - r[0] - N[0]) <= 1e-7 * inflow
+
+
 def test_periodic_box_rejects_channel_only_calls():
     L = _lbf()
     w = box_workload("pair", real="f64", n=64, xi=20)

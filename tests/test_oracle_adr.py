@@ -196,6 +196,21 @@ def test_cascade_steady_mass_balance(tiny_flow):
     assert 0 < eps < 1 and flux[1] > 0 and flux[2] > 0
 
 
+def test_production_equals_the_outflow_at_steady_state(tiny_flow):
+    # at the steady cascade nothing accumulates: what B -> C converts per step
+    # leaves as C (the paper's production rate of the final species), what
+    # A -> B converts and B -> C does not leaves as B, the rest of the inflow
+    # leaves as A
+    w, ux, uy = tiny_flow
+    g, steps, flux, inflow, eps = R.adr_steady(w.node_type, w.k, ux, uy, 3, w.tau_g, 60000,
+                                               check_every=2000, tol=1e-12)
+    r = R.adr_production(w.node_type, w.k, g)
+    assert r[1] > 0 and r[0] > r[1]
+    assert abs(r[1] - flux[2]) < 1e-8 * inflow
+    assert abs(r[0] - r[1] - flux[1]) < 1e-8 * inflow
+    assert abs(inflow - r[0] - flux[0]) < 1e-8 * inflow
+
+
 def test_first_step_removal_exact():
     # closed periodic box at rest, uniform A: after one step A has lost exactly
     # sum over links (fluid x -> catalytic x + c_i) of k w_i c_in
