@@ -83,13 +83,20 @@ typedef struct {
                             2 16-byte vectors (4 FP32 or 2 FP64 nodes per thread)   */
     int flags;           /* bit 0: disable the XCD-aware block order; bit 1: cached
                             instead of streaming (non-temporal) population accesses;
-                            bit 2: store species A unshifted in FP32 (with bit 4
-                            the A field error reaches ~2e-4 of its maximum on a
-                            512 x 128 cascade, against ~1e-6 shifted); bit 3 (batch):
+                            bit 2: store species A unshifted in FP32 (rejected
+                            together with bit 4, LBF_EINVAL: the A field error
+                            then reaches ~2e-4 of its maximum on a 512 x 128
+                            cascade, against ~1e-6 shifted); bit 3 (batch):
                             one block per tile instead of the persistent tile walk;
                             bit 4: FP32 arithmetic for FP32 storage (default: each
                             node update computes in FP64, rounding once per store);
-                            bit 5: FP32 arithmetic in the flow step only;
+                            bit 5: FP32 arithmetic in the flow step only.
+                            Bits 4 and 5 are experimental: both stay within 1e-4
+                            of the FP64 oracle over a few thousand steps but not
+                            at a steady state (2048 x 512 cascade converged: bit 4
+                            eps error 2.9e-3 and field error 2.0e-3, bit 5 field
+                            error 1.2e-4; the default FP64 arithmetic 5e-8 and
+                            4.5e-6);
                             bit 6: streaming accesses even when the lattice fits
                             the 256 MiB last-level cache (default there: cached);
                             bit 7: 64-bit population offsets in the flow and ADR

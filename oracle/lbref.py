@@ -179,9 +179,27 @@ def adr_concentration(node_type, g):
     return c
 
 
+# A steady state accumulates nothing, so every cross-section carries the
+# inflow: a check counts as steady only when the fluxes through the outlet
+# face balance the inflow of A to this fraction of it.
+MASS_BALANCE_TOL = 1e-3
+
+
+def is_steady(flux, inflow, eps, prev, tol):
+    """Steady-state reading of one check: eps changed by at most tol of itself
+    since the previous check, the final product already leaves (positive
+    outflux: before its front reaches the flux plane eps is 0 at every
+    check) and the outlet fluxes balance the inflow."""
+    if not tol > 0 or prev is None or not np.isfinite(eps) or not flux[-1] > 0:
+        return False
+    if not abs(float(np.sum(flux)) - inflow) <= MASS_BALANCE_TOL * abs(inflow):
+        return False
+    return abs(eps - prev) <= tol * abs(eps)
+
+
 def adr_steady(node_type, k, ux, uy, nspecies, tau, max_steps, check_every=1000,
                tol=1e-8, c_in=1.0, vel_scale=1.0, mode=LINK, g=None):
-    """Run until |eps(t) - eps(t-check_every)| < tol*|eps| (or max_steps).
+    """Run until a check is steady (``is_steady``), or max_steps.
 
     Returns (g, steps_done, flux, inflow, eps)."""
     if g is None:
@@ -194,7 +212,7 @@ def adr_steady(node_type, k, ux, uy, nspecies, tau, max_steps, check_every=1000,
         steps += n
         flux, inflow = adr_observe(node_type, g, c_in)
         eps = efficiency(flux)
-        if tol > 0 and prev is not None and abs(eps - prev) <= tol * abs(eps):
+        if is_steady(flux, inflow, eps, prev, tol):
             break
         prev = eps
     return g, steps, flux, inflow, eps

@@ -7,9 +7,14 @@ catalyst-placement studies.
     eps = f(k)
     eps.backward()                              # k.grad = d eps / d k
 
-Every call restarts from the state the context had when ``f`` was built (that
-pre-collision state is held fixed), sets the rates and runs the forward +
-reverse sweep of ``lbf_adr_adjoint`` on the GPU.
+The rates are those of the catalytic nodes (node type 2 or 3) in row-major
+order of the [ny, nx] lattice.  Every call restarts from the state the context
+had when ``f`` was built (that pre-collision state is held fixed), scatters
+the rates into the rate map and runs the forward + reverse sweep of
+``lbf_adr_adjoint`` on the GPU.  eps is returned as a float64 scalar on the
+device of ``k``; the gradient lands on that device with the dtype of ``k``.
+After a call the context holds that call's rates and the state T steps after
+the start, as ``lbf_adr_adjoint`` leaves it.
 """
 from __future__ import annotations
 
@@ -22,12 +27,12 @@ class _Eps(torch.autograd.Function):
     def forward(fctx, k_cat, runner):
         eps, grad_cat = runner._run(k_cat)
         fctx.save_for_backward(grad_cat)
-        return torch.tensor(eps, dtype=torch.float64)
+        return torch.tensor(eps, dtype=torch.float64, device=k_cat.device)
 
     @staticmethod
     def backward(fctx, grad_out):
         (grad_cat,) = fctx.saved_tensors
-        return grad_out * grad_cat, None
+        return grad_out.to(grad_cat.dtype) * grad_cat, None
 
 
 class EfficiencyOfRates:
@@ -41,15 +46,26 @@ class EfficiencyOfRates:
         self.T, self.M = int(T), int(ckpt_every)
         self.keep = None if keep_trace is None else bool(keep_trace)  # None: by memory
         self.start = ctx.get_state()
+        dev = ctx.device
+        self._rows = torch.as_tensor(self.cat[0], device=dev)
+        self._cols = torch.as_tensor(self.cat[1], device=dev)
+
+    @property
+    def ncat(self):
+        return int(self.cat[0].size)
 
     def _run(self, k_cat):
-        k = np.zeros(self.shape)
-        k[self.cat] = k_cat.detach().cpu().double().numpy()
+        if k_cat.shape != (self.ncat,):
+            raise ValueError(f"expected {self.ncat} rates (one per catalytic node), "
+                             f"got shape {tuple(k_cat.shape)}")
+        dev = self.ctx.device
+        k = torch.zeros(self.shape, dtype=torch.float64, device=dev)
+        k[self._rows, self._cols] = k_cat.detach().to(device=dev, dtype=torch.float64)
         self.ctx.set_rates(k)
         self.ctx.set_state(self.start)
         eps, grad = self.ctx.adjoint(self.T, self.M, self.keep)
-        g = grad.cpu()[torch.as_tensor(self.cat[0]), torch.as_tensor(self.cat[1])]
-        return eps, g.to(dtype=k_cat.dtype)
+        g = grad[self._rows, self._cols]
+        return eps, g.to(device=k_cat.device, dtype=k_cat.dtype)
 
     def __call__(self, k_cat):
         return _Eps.apply(k_cat, self)

@@ -334,17 +334,20 @@ __device__ __forceinline__ void pair_update(const AdrArgs<Real> &a, int bx, int 
             const Off PB = (Off)P * B, o = (Off)id * B;
             const PopBlock<Real, false, WIDE> vel(a.ua, 2 * PB);
             const Real u = vel.load(o), v = vel.load(o + PB);
-            Acc h[S][5];
-#pragma unroll
-            for (int s = 0; s < S; ++s)
-                pull5<Real, Acc, PairTile<Real>::NTL, WIDE>(
-                    a.src + (size_t)s * 5 * P, P, id, x, a.nx, a.nxp, m, s == 0, inlet_e, h[s]);
             if (ULDS) {
                 lmask[e] = (uint8_t)m;
                 lvel[e] = u;
                 lvel[EP + e] = v;
             }
+            // solid nodes gather nothing: their mask has no bounce-back bits,
+            // so a gather would read the neighbours' planes (past the last
+            // row of the lattice for a node of the top wall row)
             if (m != MASK5_SOLID) {
+                Acc h[S][5];
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+                    pull5<Real, Acc, PairTile<Real>::NTL, WIDE>(
+                        a.src + (size_t)s * 5 * P, P, id, x, a.nx, a.nxp, m, s == 0, inlet_e, h[s]);
                 // step-1 concentrations are recorded by the block owning the node
                 AdrArgs<Real> a1 = a;
                 const bool own = ex >= 1 && ex <= 64 && ey >= 1 && ey <= TY;

@@ -559,7 +559,7 @@ lbf_status lbf3_adr_run(lbf3_ctx c, long max_steps, int check_every, double tol,
             st = fluxes(c, o);
             if (st != LBF_OK) return st;
             const double eps = efficiency_of(o, c->p.nspecies);
-            if (!std::isnan(prev) && std::fabs(eps - prev) <= tol * std::fabs(eps)) {
+            if (lbf::steady_check(o, c->p.nspecies, o[3], eps, prev, tol)) {
                 conv = true;
                 break;
             }

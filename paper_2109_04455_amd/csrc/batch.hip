@@ -534,7 +534,7 @@ lbf_status lbf_batch_create(int n, const lbf_params *params, lbf_batch *out)
         Ctx &c = b->ctx[i];
         c.p = pi;
         c.xf = pi.flux_col == -1 ? pi.nx - 3 : pi.flux_col;
-        c.cref = (pi.real_bytes == 4 && !(pi.flags & 4)) ? pi.c_in : 0.0;
+        c.cref = storage_shift(pi);
         c.L = make_launch(pi.nx, pi.ny, pi.tile_x, pi.tile_y);
         layout(&c);
         c.valid = true;
@@ -766,7 +766,7 @@ lbf_status lbf_batch_run(lbf_batch b, long max_steps, int check_every, double to
                 prod[i] = o[4 * i + ns - 1];
                 steps_i[i] = steps;
                 b->parity_of[i] = b->gpar;
-                const bool conv = tol > 0 && !std::isnan(prev[i]) && std::fabs(e_i - prev[i]) <= tol * std::fabs(e_i);
+                const bool conv = steady_check(&o[4 * i], ns, o[4 * i + 3], e_i, prev[i], tol);
                 prev[i] = e_i;
                 if (conv) {
                     act[i] = 0;

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstddef>
 #include <cstdint>
 #include <map>
@@ -33,6 +34,32 @@ constexpr uint16_t MASK9_SOLID = 0x8000;
 constexpr int ROW_ALIGN = 64;
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Storage shift of species A: FP32 populations of A are stored as
+// g_i - w_i c_in unless flags bit 2 asks for the plain values.
+inline double storage_shift(const lbf_params &p)
+{
+    return (p.real_bytes == 4 && !(p.flags & 4)) ? p.c_in : 0.0;
+}
+
+// Steady-state test of one convergence check of an ADR run: eps moved by at
+// most tol of itself since the previous check, the outflux of the last
+// species is positive, and the outlet fluxes balance the inflow of A within
+// MASS_BALANCE_TOL of it.  A steady state has nothing accumulating, so the
+// fluxes through every cross-section equal the inflow; the two extra
+// conditions reject the quiet phase before a front reaches the flux plane,
+// when eps is 0 (or unchanged) at consecutive checks.  N: the ns outlet
+// fluxes, prev: eps at the previous check (NaN at the first).
+constexpr double MASS_BALANCE_TOL = 1e-3;
+inline bool steady_check(const double *N, int ns, double inflow, double eps, double prev,
+                         double tol)
+{
+    if (!(tol > 0) || std::isnan(prev) || std::isnan(eps) || !(N[ns - 1] > 0)) return false;
+    double tot = 0;
+    for (int s = 0; s < ns; ++s) tot += N[s];
+    if (!(std::fabs(tot - inflow) <= MASS_BALANCE_TOL * std::fabs(inflow))) return false;
+    return std::fabs(eps - prev) <= tol * std::fabs(eps);
+}
 
 // Launch shape shared by the stencil kernels: tiles of tx * ty nodes, with an
 // optional XCD-aware renumbering of blocks (consecutive tiles land on the

@@ -162,3 +162,15 @@ def test_status_strings(L):
     for s in range(0, -7, -1):
         assert L.lbf_status_str(s)
     assert L.lbf_version() >= 1
+
+
+def test_unshifted_a_with_fp32_arithmetic_rejected(L):
+    # flags bit 2 (A stored unshifted) with bit 4 (FP32 arithmetic) misses
+    # the 1e-4 accuracy bar on the A field; each alone, and FP64 storage, pass
+    st, msg = _create(L, _params(L, flags=4 | 16))
+    assert st == -1 and "bits 2 and 4" in msg
+    for f in (4, 16, 4 | 32):
+        st, msg = _create(L, _params(L, flags=f))
+        assert st == 0, msg
+    st, msg = _create(L, _params(L, flags=4 | 16, real_bytes=8))
+    assert st == 0, msg

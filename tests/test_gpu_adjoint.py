@@ -187,3 +187,51 @@ def test_steady_adjoint_two_step_equals_single_steps(real, tol):
     assert scale > 0
     assert np.abs(g2 - g1).max() <= tol * scale
     assert abs(e2 / e1 - 1) <= 1e-12
+
+
+@pytest.mark.parametrize("kdev", ["cpu", "cuda"])
+def test_efficiency_of_rates_autograd_function(tiny_ref, kdev):
+    # the torch.autograd.Function around lbf_adr_adjoint: eps(k) over the
+    # catalytic nodes' rates, backward = the adjoint gradient, on the device
+    # and in the dtype of k; checked against autograd through the torch twin
+    # of the oracle, against the entry point itself and against a central
+    # difference of eps(k) through the same function
+    from paper_2109_04455_amd.autograd import EfficiencyOfRates
+    w, flow_steps, n0, T, eps_ref, grad_ref = tiny_ref
+    c = _ctx(w, "f64")
+    c.flow_init()
+    c.flow_run(flow_steps)
+    c.adr_init()
+    c.adr_run(n0, tol=0)
+    f = EfficiencyOfRates(c, w.node_type, T, ckpt_every=200)
+    cat = np.nonzero(w.node_type >= 2)
+    assert f.ncat == cat[0].size
+    k = torch.tensor(w.k[cat], dtype=torch.float64, device=kdev, requires_grad=True)
+    eps = f(k)
+    assert eps.device == k.device and eps.dtype == torch.float64 and eps.dim() == 0
+    (3.0 * eps).backward()
+    assert k.grad.device == k.device and k.grad.dtype == k.dtype
+    g = k.grad.detach().cpu().numpy() / 3.0
+    gref = grad_ref[cat]
+    scale = np.abs(gref).max()
+    assert scale > 0
+    assert abs(eps.item() / eps_ref - 1) <= 1e-9
+    assert np.abs(g - gref).max() <= 1e-9 * scale
+    # the entry point from the same start state and rates gives the same numbers
+    c.set_rates(w.k)
+    c.set_state(f.start)
+    e2, g2 = c.adjoint(T, 200)
+    assert e2 == eps.item()
+    assert np.abs(g2.cpu().numpy()[cat] - g).max() <= 1e-15 * scale
+    # central difference at the node of the largest gradient
+    j = int(np.argmax(np.abs(gref)))
+    h = 1e-3 * float(w.k[cat][j])
+    with torch.no_grad():
+        kp = k.detach().clone()
+        kp[j] += h
+        km = k.detach().clone()
+        km[j] -= h
+        fd = (f(kp).item() - f(km).item()) / (2 * h)
+    assert abs(fd - gref[j]) <= 1e-5 * scale
+    with pytest.raises(ValueError):
+        f(k.detach()[:-1])

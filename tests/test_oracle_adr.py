@@ -18,6 +18,9 @@ cases -- never against itself:
   (Eq. source_lbm applied at the links into catalytic nodes).
 * linearity in the inlet concentration; mirror symmetry.
 * the direct sparse fixed-point solve equals the time-stepped steady state.
+* the initial state: the equilibrium's zeroth and first moments are C = c_in
+  and C u (u the scaled flow velocity), B and C absent.
+* the steady-state test of a run does not fire before the product leaves.
 """
 import numpy as np
 import pytest
@@ -421,3 +424,40 @@ def test_production_is_the_change_of_the_totals_in_a_closed_box(mode):
     assert abs(d[0] + r[0]) < 1e-12 * scale
     assert abs(d[1] - (r[0] - r[1])) < 1e-12 * scale
     assert abs(d[2] - r[1]) < 1e-12 * scale
+
+
+@pytest.mark.parametrize("c_in,scale", [(1.0, 1.0), (2.5, 0.7), (0.3, 3.0)])
+def test_adr_initial_state_moments(tiny_flow, c_in, scale):
+    # at every fluid node sum_i g_A,i = c_in and sum_i c_i g_A,i = c_in u with
+    # u = vel_scale * u_flow (the second-order equilibrium reproduces both
+    # moments exactly on D2Q5); species B and C and every solid node are 0
+    w, ux, uy = tiny_flow
+    g = R.adr_init(w.node_type, ux, uy, 3, c_in, scale)
+    fl = w.node_type == 0
+    c0 = g[0].sum(axis=0)
+    jx = (CX[:, None, None] * g[0]).sum(axis=0)
+    jy = (CY[:, None, None] * g[0]).sum(axis=0)
+    assert np.abs(c0[fl] - c_in).max() < 1e-14 * c_in
+    assert np.abs(jx[fl] - c_in * scale * ux[fl]).max() < 1e-15 * c_in
+    assert np.abs(jy[fl] - c_in * scale * uy[fl]).max() < 1e-15 * c_in
+    assert np.abs(scale * ux[fl]).max() > 1e-3   # the velocity terms matter here
+    assert (g[1:] == 0).all() and (g[:, :, ~fl] == 0).all()
+
+
+def test_steady_check_waits_for_the_product(tiny_flow):
+    # with a check every 20 steps eps is exactly 0 at the first checks (the
+    # products have not reached the flux plane), which a bare "eps did not
+    # change" test would take for a steady state; the run must continue until
+    # the product leaves and the outlet fluxes balance the inflow
+    w, ux, uy = tiny_flow
+    g = R.adr_init(w.node_type, ux, uy, 3)
+    R.adr_run(w.node_type, w.k, ux, uy, g, w.tau_g, 40)
+    flux, inflow = R.adr_observe(w.node_type, g)
+    assert R.efficiency(flux) == 0.0
+    g, steps, flux, inflow, eps = R.adr_steady(w.node_type, w.k, ux, uy, 3, w.tau_g, 60000,
+                                               check_every=20, tol=1e-8)
+    assert steps < 60000 and flux[2] > 0 and 0 < eps < 1
+    assert abs(flux.sum() - inflow) <= R.MASS_BALANCE_TOL * inflow
+    assert not R.is_steady(np.array([1.0, 0.0, 0.0]), 1.0, 0.0, 0.0, 1e-8)
+    assert not R.is_steady(np.array([0.5, 0.1, 0.1]), 1.0, 1 / 7, 1 / 7, 1e-8)
+    assert R.is_steady(np.array([0.8, 0.1, 0.1]), 1.0, 0.1, 0.1, 1e-8)

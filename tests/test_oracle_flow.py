@@ -97,3 +97,44 @@ def test_mass_flux_constant_along_channel(poiseuille):
         nx = t.shape[1]
         j = (rho * ux)[1:-1, : nx // 2].sum(axis=0)
         assert np.abs(j - j[0]).max() < 1e-6 * abs(j[0])
+
+
+@pytest.mark.parametrize("u0,ny", [(0.05, 18), (0.02, 34), (0.08, 25)])
+def test_inlet_centreline_velocity_is_u0(u0, ny):
+    # the inlet column carries the parabola whose zeros are the half-way walls
+    # y = 1/2 and y = ny - 3/2 and whose value at the centre line is u0: fit
+    # its amplitude from the oracle's own moments after some steps and
+    # compare the centre-line value with u0
+    nx = 24
+    t = channel(nx, ny)
+    f = R.flow_init(t, u0)
+    R.flow_run(t, f, TAU, u0, 200)
+    ux, uy = R.flow_velocity(t, f)
+    y = np.arange(1, ny - 1)
+    par = (y - 0.5) * (ny - 1.5 - y)
+    a = (ux[1:-1, 0] * par).sum() / (par * par).sum()
+    yc = (ny - 1) / 2.0
+    centre = a * (yc - 0.5) * (ny - 1.5 - yc)
+    assert abs(centre - u0) < 1e-12 * u0
+    assert np.abs(ux[1:-1, 0] - a * par).max() < 1e-13 * u0
+    assert np.abs(uy[1:-1, 0]).max() < 1e-13 * u0
+
+
+def test_poiseuille_mass_flux_profile_absolute(poiseuille):
+    # developed plane Poiseuille flow half-way down the channel: the mass flux
+    # density rho u_x is the parabola 4 u0 (y - 1/2)(ny - 3/2 - y) / H^2 of
+    # the inlet, carrying the inlet's mass flux (the lattice is weakly
+    # compressible: rho falls along the channel with the pressure, so u_x
+    # itself rises by the same factor).  Within 1e-3 u0 at H = 32, with a
+    # second-order wall error (about 4x larger at H = 16).
+    errs = {}
+    for h, (t, ux, uy, rho) in poiseuille.items():
+        ny, nx = t.shape
+        y = np.arange(1, ny - 1)
+        u_in = 4 * U0 * (y - 0.5) * (ny - 1.5 - y) / h ** 2
+        j_in = (rho[1:-1, 0] * ux[1:-1, 0]).sum()
+        j_mid = rho[1:-1, nx // 2] * ux[1:-1, nx // 2]
+        assert abs(j_mid.sum() - j_in) < 1e-6 * j_in
+        errs[h] = np.abs(j_mid - u_in * j_in / u_in.sum()).max() / U0
+    assert errs[32] < 1e-3
+    assert 3.0 < errs[16] / errs[32] < 5.0
