@@ -199,7 +199,10 @@ lbf_status lbf_adr_steps(lbf_ctx ctx, long *steps);
 
 /* Adjoint (reverse-mode) gradient of eps with respect to the rate k(x).
  * Objective: eps after T further steps from the current state, the current
- * pre-collision populations held fixed.  On return the context has advanced
+ * pre-collision populations held fixed: the window's first collision and
+ * reaction use the rates set at the call (the current post-collision lattice
+ * is recomputed from the previous one), so eps_out and the gradient describe
+ * the same function of k also after lbf_set_rates.  On return the context has advanced
  * T steps exactly as lbf_adr_run(T) would, *eps_out holds eps, and
  * grad_k_dev (device double [ny][nx]) holds d eps / d k at catalytic nodes
  * and 0 elsewhere.  The forward pass stores the full state every ckpt_every

@@ -541,6 +541,13 @@ lbf_status lbf_adr_adjoint(lbf_ctx c, long T, int M, int keep, void *ws, size_t 
     if (e != hipSuccess) return hip_fail(c, e, "fill");
 
     auto slot = [&](size_t base, long j) { return (void *)(W + base + (size_t)j * L.slot); };
+    // The objective holds the pre-collision state fixed; the current lattice
+    // is its collided form with the rates of the step that made it.  Redo
+    // that collision (one step from the previous lattice) with the rates set
+    // now, so that eps_out is the efficiency of these rates, consistent with
+    // the gradient, also after lbf_set_rates changed them.
+    e = enqueue_adr_step(c, c->gpar ^ 1, s, nullptr);
+    if (e != hipSuccess) return hip_fail(c, e, "window start");
     // C at the trace nodes for the window's first step (pre-collision state
     // pulled from the lattice before the current one)
     {
