@@ -234,6 +234,14 @@ lbf_status lbf_state_bytes(lbf_ctx ctx, size_t *bytes);
 lbf_status lbf_get_state(lbf_ctx ctx, void *dst_dev);
 lbf_status lbf_set_state(lbf_ctx ctx, const void *src_dev);
 
+/* Capture and instantiate the HIP graphs that lbf_adr_run and
+ * lbf_time_adr_steps replay for a block of nsteps ADR steps (blocks are at
+ * most 1000 steps), from either lattice, without running them: a timed or
+ * latency-critical loop then pays no capture cost.  Needs the geometry set
+ * and a bound workspace; the graphs are dropped by lbf_bind and
+ * lbf_set_geometry.  Host and driver work only. */
+lbf_status lbf_prepare_adr_steps(lbf_ctx ctx, long nsteps);
+
 /* Timing helper: enqueue exactly nsteps ADR steps between two HIP events
  * recorded on the bound stream and return the elapsed milliseconds (the
  * average duration of one step kernel is ms / nsteps).  Synchronises. */

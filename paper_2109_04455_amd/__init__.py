@@ -274,6 +274,10 @@ class Context:
         self._call("lbf_set_state", ctypes.c_void_p(buf.data_ptr()))
 
     # ---------------------------------------------------------------- timing
+    def prepare_adr_steps(self, nsteps):
+        """Instantiate the step-block graphs of nsteps ADR steps ahead of use."""
+        self._call("lbf_prepare_adr_steps", int(nsteps))
+
     def time_adr_steps(self, nsteps):
         ms = ctypes.c_double()
         self._call("lbf_time_adr_steps", int(nsteps), ctypes.byref(ms))

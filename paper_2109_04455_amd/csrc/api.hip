@@ -145,24 +145,10 @@ hipError_t enqueue_flow_step(Ctx *c, int src_buf, bool write_u, hipStream_t s)
                             flow_args<double>(c, src_buf), s);
 }
 
-// Replay (capturing on first use) a graph of n consecutive steps.
-lbf_status run_steps(Ctx *c, int kind, long n)
+// The instantiated graph of n consecutive steps starting from lattice par
+// (captured and instantiated on first use).
+lbf_status graph_of(Ctx *c, int kind, long n, int par, hipGraphExec_t *out)
 {
-    if (n <= 0) return LBF_OK;
-    int &par = kind == KIND_ADR ? c->gpar : c->fpar;
-    if (n < GRAPH_MIN_STEPS) {
-        if (kind == KIND_ADR) {
-            hipError_t e = enqueue_adr_block(c, par, n, c->stream);
-            if (e != hipSuccess) return hip_fail(c, e, "step launch");
-            return LBF_OK;
-        }
-        for (long i = 0; i < n; ++i) {
-            hipError_t e = enqueue_flow_step(c, par, i == n - 1, c->stream);
-            if (e != hipSuccess) return hip_fail(c, e, "step launch");
-            par ^= 1;
-        }
-        return LBF_OK;
-    }
     const auto key = std::make_tuple(kind, n, par);
     auto it = c->graphs.find(key);
     if (it == c->graphs.end()) {
@@ -189,7 +175,32 @@ lbf_status run_steps(Ctx *c, int kind, long n)
         if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
         it = c->graphs.emplace(key, ex).first;
     }
-    hipError_t e = hipGraphLaunch(it->second, c->stream);
+    *out = it->second;
+    return LBF_OK;
+}
+
+// Replay (capturing on first use) a graph of n consecutive steps.
+lbf_status run_steps(Ctx *c, int kind, long n)
+{
+    if (n <= 0) return LBF_OK;
+    int &par = kind == KIND_ADR ? c->gpar : c->fpar;
+    if (n < GRAPH_MIN_STEPS) {
+        if (kind == KIND_ADR) {
+            hipError_t e = enqueue_adr_block(c, par, n, c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "step launch");
+            return LBF_OK;
+        }
+        for (long i = 0; i < n; ++i) {
+            hipError_t e = enqueue_flow_step(c, par, i == n - 1, c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "step launch");
+            par ^= 1;
+        }
+        return LBF_OK;
+    }
+    hipGraphExec_t ex = nullptr;
+    lbf_status st = graph_of(c, kind, n, par, &ex);
+    if (st != LBF_OK) return st;
+    hipError_t e = hipGraphLaunch(ex, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
     const long swaps = kind == KIND_ADR ? n - adr_pairs(c, n) : n;
     if (swaps & 1) par ^= 1;
@@ -769,6 +780,23 @@ static lbf_status time_steps(lbf_ctx c, int kind, long nsteps, double *ms)
     if (st != LBF_OK) return st;
     if (e != hipSuccess) return hip_fail(c, e, "timing events");
     if (ms) *ms = t;
+    return LBF_OK;
+}
+
+lbf_status lbf_prepare_adr_steps(lbf_ctx c, long nsteps)
+{
+    lbf_status st = check_ready(c, true);
+    if (st != LBF_OK) return st;
+    if (nsteps < 1) return fail(c, LBF_EINVAL, "nsteps < 1");
+    // lbf_adr_run and lbf_time_adr_steps split runs into blocks of at most
+    // block_steps steps; blocks below GRAPH_MIN_STEPS launch directly
+    const long n = std::min<long>(nsteps, c->block_steps);
+    if (n < GRAPH_MIN_STEPS) return LBF_OK;
+    for (int par = 0; par < 2; ++par) {
+        hipGraphExec_t ex = nullptr;
+        st = graph_of(c, KIND_ADR, n, par, &ex);
+        if (st != LBF_OK) return st;
+    }
     return LBF_OK;
 }
 
