@@ -107,7 +107,12 @@ typedef struct {
                             link-reaction channel run two per launch, the
                             intermediate state kept in LDS; the last step of
                             every block is a single one); the adjoint's steps
-                            likewise */
+                            likewise;
+                            bit 9: untraced two-step launches by wavefronts that
+                            march along y with the intermediate rows in
+                            registers instead of the LDS tile (FP32 storage with
+                            FP64 arithmetic; results identical, slower on this
+                            part) */
     int boundary;        /* 0: channel (solid rows 0 and ny-1, inlet at x = 0,
                             outlet at x = nx-1); 1: box periodic in x and y with no
                             inlet or outlet (ADR only: no flow solve, no fluxes,

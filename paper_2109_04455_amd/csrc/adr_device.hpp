@@ -97,15 +97,18 @@ __device__ __forceinline__ void periodic_neighbours(int x, int y, int nx, int ny
     nb[DS] = (size_t)ym * nxp + x;
 }
 
-// BGK collision of one species in shifted form (cref = 0 for B and C).
-template <typename Acc>
-__device__ __forceinline__ void collide5(Acc (&h)[5], Acc delta, Acc cref, const Acc (&p)[5],
-                                         Acc omega)
+// BGK collision of one species in shifted form: the equilibrium of
+// population i is w_i p_i cref + w_i (1 + p_i) delta, written as
+// off[i] + mul[i] delta with the per-node factors mul[i] = w_i (1 + p_i) and
+// off[i] = w_i p_i cref computed once for all species (off = 0 for B and C,
+// whose cref is 0).
+template <typename Acc, bool OFF>
+__device__ __forceinline__ void collide5(Acc (&h)[5], Acc delta, const Acc (&mul)[5],
+                                         const Acc (&off)[5], Acc omega)
 {
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-        const Acc w = w5<Acc>(i);
-        const Acc target = w * p[i] * cref + w * (Acc(1) + p[i]) * delta;
+        const Acc target = OFF ? off[i] + mul[i] * delta : mul[i] * delta;
         h[i] -= omega * (h[i] - target);
     }
 }
@@ -131,15 +134,28 @@ template <typename Real, typename Acc, int S, bool TRACE, int MODE = 0>
 __device__ __forceinline__ void collide_react(const AdrArgs<Real> &a, size_t id, unsigned m, Acc u,
                                               Acc v, Acc (&h)[S][5], const size_t *nb = nullptr)
 {
-    Acc p[5];
-    eq_factors(u, v, p);
+    Acc mul[5], off[5];
+    {
+        Acc p[5];
+        eq_factors(u, v, p);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            const Acc w = w5<Acc>(i), wp = w * p[i];
+            // FP32 arithmetic keeps 1 + p_i together: w + w p_i loses more of
+            // the small p_i in single precision
+            mul[i] = sizeof(Acc) == 4 ? w * (Acc(1) + p[i]) : w + wp;
+            off[i] = wp * Acc(a.cref);
+        }
+    }
     Acc c[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const Acc delta = h[s][0] + h[s][1] + h[s][2] + h[s][3] + h[s][4];
-        const Acc cref = s == 0 ? Acc(a.cref) : Acc(0);
-        c[s] = cref + delta;
-        collide5(h[s], delta, cref, p, Acc(a.omega));
+        c[s] = (s == 0 ? Acc(a.cref) : Acc(0)) + delta;
+        if (s == 0)
+            collide5<Acc, true>(h[s], delta, mul, off, Acc(a.omega));
+        else
+            collide5<Acc, false>(h[s], delta, mul, off, Acc(a.omega));
     }
     if (m & 0xF0u) {
         const int off[5] = {0, 1, a.nxp, -1, -a.nxp};
@@ -288,105 +304,180 @@ struct PairTile {
     static constexpr int TX = 64, TY = EY - 2;  // output nodes per block
 };
 
+// LDS of one two-step tile: the step-1 populations of the extended tile and,
+// with ULDS, its masks and velocities.
+template <typename Real, int S>
+struct PairLds {
+    static constexpr int EY = PairTile<Real>::EY, EX = 66, EP = EX * EY;
+    static constexpr bool ULDS = PairTile<Real>::ULDS;
+    Real pop[5 * S * EP];
+    Real vel[ULDS ? 2 * EP : 1];
+    uint8_t mask[ULDS ? EP : 1];
+};
+
+// The extended-tile node a thread updates in step 1 of tile (bx, by):
+// wavefront w < EY takes the 64 core nodes of extended row w, wavefront EY
+// the two ring columns of every row.
+struct PairNode {
+    int ex, ey, x, y, e;
+    bool inside;
+    size_t id;
+};
+
+template <typename Real>
+__device__ __forceinline__ PairNode pair_node(const AdrArgs<Real> &a, int bx, int by)
+{
+    constexpr int EY = PairTile<Real>::EY, EX = 66, TY = EY - 2;
+    const int w = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
+    PairNode n;
+    if (w < EY) {
+        n.ey = w;
+        n.ex = lane + 1;
+    } else {
+        n.ey = lane >> 1;
+        n.ex = (lane & 1) ? EX - 1 : 0;
+    }
+    n.x = bx * 64 - 1 + n.ex;
+    n.y = by * TY - 1 + n.ey;
+    n.inside = n.ey < EY && n.x >= 0 && n.x < a.nx && n.y >= 0 && n.y < a.ny;
+    n.id = (size_t)(n.inside ? n.y : 0) * a.nxp + (n.inside ? n.x : 0);
+    n.e = n.ey * EX + n.ex;
+    return n;
+}
+
+// What step 1 of a node reads before its gather: mask and velocity.
+template <typename Real>
+struct PairPre {
+    unsigned m;
+    Real u, v;
+};
+
+template <typename Real, bool WIDE>
+__device__ __forceinline__ PairPre<Real> pair_pre(const AdrArgs<Real> &a, const PairNode &n)
+{
+    PairPre<Real> q{MASK5_SOLID, Real(0), Real(0)};
+    if (n.inside) {
+        using Off = off_t_<WIDE>;
+        constexpr Off B = sizeof(Real);
+        const Off PB = (Off)a.plane * B, o = (Off)n.id * B;
+        const PopBlock<Real, false, WIDE> vel(a.ua, 2 * PB);
+        q.m = a.mask5[n.id];
+        q.u = vel.load(o);
+        q.v = vel.load(o + PB);
+    }
+    return q;
+}
+
+// Step 1 of a node into the LDS tile.
+template <typename Real, typename Acc, int S, bool WIDE, bool TRACE>
+__device__ __forceinline__ void pair_step1(PairLds<Real, S> &L, const AdrArgs<Real> &a,
+                                           const PairNode &n, const PairPre<Real> &q)
+{
+    constexpr int EY = PairTile<Real>::EY, TY = EY - 2, EP = PairLds<Real, S>::EP;
+    if (!n.inside) return;
+    if (PairLds<Real, S>::ULDS) {
+        L.mask[n.e] = (uint8_t)q.m;
+        L.vel[n.e] = q.u;
+        L.vel[EP + n.e] = q.v;
+    }
+    // solid nodes gather nothing: their mask has no bounce-back bits, so a
+    // gather would read the neighbours' planes (past the last row of the
+    // lattice for a node of the top wall row)
+    if (q.m == MASK5_SOLID) return;
+    const size_t P = a.plane;
+    const Acc inlet_e = Acc(2) * w5<Acc>(DE) * (Acc(a.cin) - Acc(a.cref));
+    Acc h[S][5];
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+        pull5<Real, Acc, PairTile<Real>::NTL, WIDE>(a.src + (size_t)s * 5 * P, P, n.id, n.x, a.nx,
+                                                    a.nxp, q.m, s == 0, inlet_e, h[s]);
+    if constexpr (TRACE) {
+        // step-1 concentrations are recorded by the block owning the node
+        AdrArgs<Real> a1 = a;
+        const bool own = n.ex >= 1 && n.ex <= 64 && n.ey >= 1 && n.ey <= TY;
+        a1.trace = own ? a.trace : nullptr;
+        collide_react<Real, Acc, S, TRACE>(a1, n.id, q.m, Acc(q.u), Acc(q.v), h);
+    } else {
+        collide_react<Real, Acc, S, false>(a, n.id, q.m, Acc(q.u), Acc(q.v), h);
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) L.pop[(s * 5 + i) * EP + n.e] = Real(h[s][i]);
+}
+
+// Step 2 of this thread's output node of tile (bx, by) from the LDS tile:
+// returns false when the thread has no fluid output node, else the node
+// index and its post-collision populations in h.  The ring nodes a gather
+// can reach (x - 1 for x > 0, x + 1 for x < nx - 1, y +- 1 of a fluid node)
+// were all updated in step 1; ring nodes outside the lattice are never read
+// (inlet and outlet rules, solid channel walls).
+template <typename Real, typename Acc, int S, bool WIDE, bool TRACE>
+__device__ __forceinline__ bool pair_step2(const PairLds<Real, S> &L, const AdrArgs<Real> &a,
+                                           int bx, int by, size_t &id, Acc (&h)[S][5])
+{
+    constexpr int EY = PairTile<Real>::EY, EX = 66, TY = EY - 2, EP = PairLds<Real, S>::EP;
+    constexpr bool ULDS = PairLds<Real, S>::ULDS;
+    const int w = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
+    if (w >= TY) return false;
+    const int x = bx * 64 + lane, y = by * TY + w;
+    if (x >= a.nx || y >= a.ny) return false;
+    id = (size_t)y * a.nxp + x;
+    const int e = (w + 1) * EX + lane + 1;
+    const unsigned m = ULDS ? L.mask[e] : a.mask5[id];
+    if (m == MASK5_SOLID) return false;
+    constexpr uint32_t LB = sizeof(Real);
+    const Acc inlet_e = Acc(2) * w5<Acc>(DE) * (Acc(a.cin) - Acc(a.cref));
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+        pull5_at<Acc>(LdsBlock<Real>{L.pop + s * 5 * EP}, (uint32_t)(EP * LB), (uint32_t)(EX * LB),
+                      (uint32_t)e * LB, x, a.nx, m, s == 0, inlet_e, h[s]);
+    Acc u, v;
+    if (ULDS) {
+        u = Acc(L.vel[e]);
+        v = Acc(L.vel[EP + e]);
+    } else {
+        using Off = off_t_<WIDE>;
+        constexpr Off B = sizeof(Real);
+        const Off PB = (Off)a.plane * B, o = (Off)id * B;
+        const PopBlock<Real, false, WIDE> vel(a.ua, 2 * PB);
+        u = Acc(vel.load(o));
+        v = Acc(vel.load(o + PB));
+    }
+    if constexpr (TRACE) {
+        AdrArgs<Real> a2 = a;
+        a2.trace = a.trace2;
+        collide_react<Real, Acc, S, TRACE>(a2, id, m, u, v, h);
+    } else {
+        collide_react<Real, Acc, S, false>(a, id, m, u, v, h);
+    }
+    return true;
+}
+
 // Two steps per launch (temporal blocking).  A block owns 64 x (EY - 2)
 // output nodes (rows aligned to 64 nodes) and the extended tile of 66 x EY
 // nodes around them (a ring of one node).  Step 1 updates the extended tile
 // from the lattice in HBM and keeps the result in LDS, rounded to Real
-// exactly as a store to HBM would round it: wavefront w < EY takes the 64
-// core nodes of extended row w, wavefront EY the two ring columns of every
-// row.  Step 2 gathers the output nodes from LDS, one row per wavefront, and
-// writes them.  A ring node is computed by every block whose tile it borders;
-// its source reads mostly hit the L2 that the XCD-aware block order shares
-// between neighbouring tiles.  The lattice crosses HBM once per two steps.
-// Tile shape, occupancy target, the cache hint of the step-1 loads and
-// whether masks and velocities stay in LDS (step 2 then reads global memory
-// only for reaction rates) come from PairTile.  NT: streaming hint on the
-// final stores.  Callers launch 64 x (EY + 1) threads per block.
+// exactly as a store to HBM would round it.  Step 2 gathers the output nodes
+// from LDS, one row per wavefront, and writes them.  A ring node is computed
+// by every block whose tile it borders; its source reads mostly hit the L2
+// that the XCD-aware block order shares between neighbouring tiles.  The
+// lattice crosses HBM once per two steps.  Tile shape, occupancy target, the
+// cache hint of the step-1 loads and whether masks and velocities stay in
+// LDS (step 2 then reads global memory only for reaction rates) come from
+// PairTile.  NT: streaming hint on the final stores.  Callers launch
+// 64 x (EY + 1) threads per block.
 template <typename Real, typename Acc, int S, bool NT, bool WIDE, bool TRACE>
 __device__ __forceinline__ void pair_update(const AdrArgs<Real> &a, int bx, int by)
 {
-    constexpr int EY = PairTile<Real>::EY, EX = 66, TY = EY - 2, EP = EX * EY;
-    constexpr bool ULDS = PairTile<Real>::ULDS;
-    __shared__ Real lds[5 * S * EP];
-    __shared__ Real lvel[ULDS ? 2 * EP : 1];
-    __shared__ uint8_t lmask[ULDS ? EP : 1];
-    using Off = off_t_<WIDE>;
-    constexpr Off B = sizeof(Real);
-    const int x0 = bx * 64, y0 = by * TY;  // first output node
-    const int w = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
-    const size_t P = a.plane;
-    const Acc inlet_e = Acc(2) * w5<Acc>(DE) * (Acc(a.cin) - Acc(a.cref));
-    {
-        int ex, ey;
-        if (w < EY) {
-            ey = w;
-            ex = lane + 1;
-        } else {
-            ey = lane >> 1;
-            ex = (lane & 1) ? EX - 1 : 0;
-        }
-        const int x = x0 - 1 + ex, y = y0 - 1 + ey;
-        const bool inside = ey < EY && x >= 0 && x < a.nx && y >= 0 && y < a.ny;
-        const size_t id = (size_t)y * a.nxp + x;
-        const int e = ey * EX + ex;
-        if (inside) {
-            const unsigned m = a.mask5[id];
-            const Off PB = (Off)P * B, o = (Off)id * B;
-            const PopBlock<Real, false, WIDE> vel(a.ua, 2 * PB);
-            const Real u = vel.load(o), v = vel.load(o + PB);
-            if (ULDS) {
-                lmask[e] = (uint8_t)m;
-                lvel[e] = u;
-                lvel[EP + e] = v;
-            }
-            // solid nodes gather nothing: their mask has no bounce-back bits,
-            // so a gather would read the neighbours' planes (past the last
-            // row of the lattice for a node of the top wall row)
-            if (m != MASK5_SOLID) {
-                Acc h[S][5];
-#pragma unroll
-                for (int s = 0; s < S; ++s)
-                    pull5<Real, Acc, PairTile<Real>::NTL, WIDE>(
-                        a.src + (size_t)s * 5 * P, P, id, x, a.nx, a.nxp, m, s == 0, inlet_e, h[s]);
-                // step-1 concentrations are recorded by the block owning the node
-                AdrArgs<Real> a1 = a;
-                const bool own = ex >= 1 && ex <= 64 && ey >= 1 && ey <= TY;
-                a1.trace = own ? a.trace : nullptr;
-                collide_react<Real, Acc, S, TRACE>(a1, id, m, Acc(u), Acc(v), h);
-#pragma unroll
-                for (int s = 0; s < S; ++s)
-#pragma unroll
-                    for (int i = 0; i < 5; ++i) lds[(s * 5 + i) * EP + e] = Real(h[s][i]);
-            }
-        }
-    }
+    __shared__ PairLds<Real, S> L;
+    const PairNode n = pair_node(a, bx, by);
+    pair_step1<Real, Acc, S, WIDE, TRACE>(L, a, n, pair_pre<Real, WIDE>(a, n));
     __syncthreads();
-    // Step 2 on the output rows.  The ring nodes a gather can reach (x - 1
-    // for x > 0, x + 1 for x < nx - 1, y +- 1 of a fluid node) were all
-    // updated above; ring nodes outside the lattice are never read (inlet and
-    // outlet rules, solid channel walls).
-    if (w >= TY) return;
-    const int x = x0 + lane, y = y0 + w;
-    if (x >= a.nx || y >= a.ny) return;
-    const size_t id = (size_t)y * a.nxp + x;
-    const int e = (w + 1) * EX + lane + 1;
-    const unsigned m = ULDS ? lmask[e] : a.mask5[id];
-    if (m == MASK5_SOLID) return;
-    constexpr uint32_t LB = sizeof(Real);
+    size_t id;
     Acc h[S][5];
-#pragma unroll
-    for (int s = 0; s < S; ++s)
-        pull5_at<Acc>(LdsBlock<Real>{lds + s * 5 * EP}, (uint32_t)(EP * LB),
-                                 (uint32_t)(EX * LB), (uint32_t)e * LB, x, a.nx, m, s == 0,
-                                 inlet_e, h[s]);
-    AdrArgs<Real> a2 = a;
-    a2.trace = a.trace2;
-    if (ULDS) {
-        collide_react<Real, Acc, S, TRACE>(a2, id, m, Acc(lvel[e]), Acc(lvel[EP + e]), h);
-        store_node<Real, Acc, S, NT, WIDE>(a2, id, h);
-    } else {
-        collide_react_store<Real, Acc, S, TRACE, NT, WIDE>(a2, id, m, h);
-    }
+    if (pair_step2<Real, Acc, S, WIDE, TRACE>(L, a, bx, by, id, h))
+        store_node<Real, Acc, S, NT, WIDE>(a, id, h);
 }
 
 }  // namespace adr

@@ -119,6 +119,10 @@ hipError_t enqueue_adr_pair(Ctx *c, int src_buf, hipStream_t s)
 {
     AdrArgs<float> af = adr_args<float>(c, src_buf);
     AdrArgs<double> ad = adr_args<double>(c, src_buf);
+    if (c->march) {
+        af.L = c->Lm;
+        return launch_adr_march(c->p.nspecies, af, s);
+    }
     af.L = ad.L = c->Lp;
     return launch_adr_pair(c->p.real_bytes, c->p.nspecies, af, ad, s);
 }
@@ -351,6 +355,10 @@ lbf_status lbf_create(const lbf_params *p, lbf_ctx *out)
         c->Lp.gx = t.gx;
         c->Lp.gy = t.gy;
         c->Lp.vec = false;
+        // flags bit 9: marching wavefronts instead of the LDS tile (FP32
+        // storage with FP64 arithmetic and 32-bit offsets only)
+        c->march = (p->flags & 512) && p->real_bytes == 4 && !c->Lp.fp32_math && !c->Lp.wide;
+        if (c->march) c->Lm = march_launch(c->Lp, p->nx, p->ny, 22);
     }
     c->flow_fp32_math = (p->flags & (16 | 32)) != 0;
     c->valid = true;

@@ -20,7 +20,9 @@ struct lbf_ctx_s {
     lbf::Launch L;   // one node per thread
     lbf::Launch Lv;  // ADR step launch (vectorised or not, per params.variant)
     lbf::Launch Lp;  // two-step ADR launch (when `pair`)
+    lbf::Launch Lm;  // marching two-step launch (when `march`)
     bool pair = false;  // untraced ADR steps run two per launch
+    bool march = false;  // ... by the marching kernel instead of the LDS tile
     bool flow_fp32_math = false;  // flow step computes in FP32 (FP32 storage)
 
     // workspace (caller-owned) and its layout

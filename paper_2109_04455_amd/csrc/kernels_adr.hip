@@ -18,6 +18,7 @@
 // with bounce-back for the other species, outlet C_w = C_b, outflux plane
 // two nodes before the right boundary).
 #include "adr_device.hpp"
+#include "adr_march.hpp"
 
 namespace lbf {
 namespace {
@@ -148,6 +149,23 @@ __attribute__((amdgpu_waves_per_eu(adr::PairTile<Real>::OCC))) void k_adr_step2(
     int bx, by;
     tile_of_block(a.L, bx, by);
     adr::pair_update<Real, Acc, S, NT, WIDE, TRACE>(a, bx, by);
+}
+
+// Two steps per launch by marching wavefronts (adr_march.hpp): block b holds
+// MARCH_WAVES strips side by side in x; strips of odd strip rows march down.
+template <int S, bool NT, int H>
+__global__ __launch_bounds__(64 * adr::MARCH_WAVES)
+__attribute__((amdgpu_waves_per_eu(3))) void k_adr_march(AdrArgs<float> a)
+{
+    int bx, by;
+    tile_of_block(a.L, bx, by);
+    const int x0 = (bx * adr::MARCH_WAVES + (int)(threadIdx.x >> 6)) * 64;
+    if (x0 >= a.nx) return;  // a whole wavefront past the lattice
+    const int y0 = by * H;
+    if (by & 1)
+        adr::march_strip<S, NT, -1, H>(a, x0, y0);
+    else
+        adr::march_strip<S, NT, 1, H>(a, x0, y0);
 }
 
 // Reaction variant and/or periodic box (FP64 arithmetic, no trace).
@@ -520,7 +538,8 @@ hipError_t step_dispatch(int ns, bool trace, const AdrArgs<Real> &a, hipStream_t
 template <typename Real, typename Acc, int S>
 void pair_launch(const AdrArgs<Real> &a, hipStream_t s)
 {
-    const dim3 g = a.L.grid(), b(64 * (adr::PairTile<Real>::EY + 1));
+    const dim3 b(64 * (adr::PairTile<Real>::EY + 1));
+    const dim3 g = a.L.grid();
     const int sel = (a.L.nontemporal ? 1 : 0) | (a.L.wide ? 2 : 0) | (a.trace || a.trace2 ? 4 : 0);
     switch (sel) {
     case 0: hipLaunchKernelGGL((k_adr_step2<Real, Acc, S, false, false, false>), g, b, 0, s, a); break;
@@ -549,6 +568,43 @@ hipError_t pair_dispatch(int ns, const AdrArgs<Real> &a, hipStream_t s)
 }
 
 }  // namespace
+
+Launch march_launch(const Launch &base, int nx, int ny, int h)
+{
+    Launch L = base;
+    L.tx = 64 * adr::MARCH_WAVES;
+    L.ty = h;  // strip height; blocks are 64 * MARCH_WAVES threads
+    const int strips = (nx + 63) / 64;
+    L.gx = (strips + adr::MARCH_WAVES - 1) / adr::MARCH_WAVES;
+    L.gy = (ny + h - 1) / h;
+    L.vec = false;
+    return L;
+}
+
+hipError_t launch_adr_march(int ns, const AdrArgs<float> &a, hipStream_t s)
+{
+    if (a.L.tx != 64 * adr::MARCH_WAVES || a.L.wide || a.L.fp32_math || a.L.mode != 0 ||
+        a.L.periodic || a.trace || a.trace2)
+        return hipErrorInvalidValue;
+    const dim3 g = a.L.grid(), b(64 * adr::MARCH_WAVES);
+    const bool nt = a.L.nontemporal;
+#define LBF_MARCH(H)                                                                   \
+    if (a.L.ty == H) {                                                                 \
+        if (ns == 2 && nt)                                                             \
+            hipLaunchKernelGGL((k_adr_march<2, true, H>), g, b, 0, s, a);              \
+        else if (ns == 2)                                                              \
+            hipLaunchKernelGGL((k_adr_march<2, false, H>), g, b, 0, s, a);             \
+        else if (nt)                                                                   \
+            hipLaunchKernelGGL((k_adr_march<3, true, H>), g, b, 0, s, a);              \
+        else                                                                           \
+            hipLaunchKernelGGL((k_adr_march<3, false, H>), g, b, 0, s, a);             \
+        return hipGetLastError();                                                      \
+    }
+    LBF_MARCH(22)
+#undef LBF_MARCH
+    return hipErrorInvalidValue;
+    return hipGetLastError();
+}
 
 void pair_tile(int real_bytes, int &tx, int &ty)
 {

@@ -143,6 +143,10 @@ hipError_t launch_adr_init(int real_bytes, int ns, const AdrArgs<float> &af,
 hipError_t launch_adr_pair(int real_bytes, int ns, const AdrArgs<float> &af,
                            const AdrArgs<double> &ad, hipStream_t s);
 void pair_tile(int real_bytes, int &tx, int &ty);
+// Two ADR steps per launch by wavefronts marching along y (FP32 storage,
+// FP64 arithmetic, link reactions in a channel, 32-bit offsets, no trace).
+Launch march_launch(const Launch &base, int nx, int ny, int strip_rows);
+hipError_t launch_adr_march(int ns, const AdrArgs<float> &a, hipStream_t s);
 hipError_t launch_adr_step(int real_bytes, int ns, bool trace, const AdrArgs<float> &af,
                            const AdrArgs<double> &ad, hipStream_t s);
 hipError_t launch_flux(int real_bytes, int ns, const void *src, const uint8_t *mask5, int nx, int ny,

@@ -174,3 +174,4 @@ def test_unshifted_a_with_fp32_arithmetic_rejected(L):
         assert st == 0, msg
     st, msg = _create(L, _params(L, flags=4 | 16, real_bytes=8))
     assert st == 0, msg
+
