@@ -50,7 +50,7 @@ struct AdjArgs {
     double *acc;          // [ntrace][4] per-link gradient accumulators
     int nx, ny, nxp;
     size_t plane;
-    Real omega;
+    double omega;
     Launch L;
 };
 
@@ -90,53 +90,58 @@ __device__ __forceinline__ void adj_gather(const BlkOf &blk_of, Off PB, Off RB, 
 
 // The local part of one adjoint step at fluid node id: the gradient terms of
 // its catalytic links (added to the accumulators when `own`), then
-// nu(m) = (R Col)^T lam into out.  trace: (C_A, C_B) of step m.
+// nu(m) = (R Col)^T lam into out.  trace: (C_A, C_B) of step m.  The node
+// arithmetic is FP64 whatever the storage type, as in the forward collision.
 template <typename Real, int S>
 __device__ __forceinline__ void adj_local(const AdjArgs<Real> &a, const Real *trace, size_t id,
-                                          unsigned m, Real u, Real v, bool own,
-                                          const Real (&lam)[S][5], Real (&out)[S][5])
+                                          unsigned m, Real u_, Real v_, bool own,
+                                          const Real (&lam_)[S][5], Real (&out)[S][5])
 {
-    Real rsrc[S];
+    double lam[S][5], rsrc[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) rsrc[s] = 0;
+    for (int s = 0; s < S; ++s) {
+        rsrc[s] = 0;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) lam[s][i] = (double)lam_[s][i];
+    }
     if (m & 0xF0u) {
         const int off[5] = {0, 1, a.nxp, -1, -a.nxp};
         const int t = a.trace_idx[id];
-        const Real ca = trace[2 * t], cb = trace[2 * t + 1];
+        const double ca = (double)trace[2 * t], cb = (double)trace[2 * t + 1];
 #pragma unroll
         for (int i = 1; i < 5; ++i) {
             if (!((m >> (3 + i)) & 1u)) continue;
             const size_t sid = id + off[i];
-            const Real kap = a.kr[sid] * w5<Real>(i);
+            const double kap = (double)a.kr[sid] * w5<double>(i);
             double g;
             if (a.type[sid] == 2) {
-                const Real d = lam[1][i] - lam[0][i];
-                g = (double)w5<Real>(i) * (double)ca * (double)d;
+                const double d = lam[1][i] - lam[0][i];
+                g = w5<double>(i) * ca * d;
                 rsrc[0] += kap * d;
             } else {
-                const Real d = lam[S - 1][i] - lam[1][i];
-                g = (double)w5<Real>(i) * (double)cb * (double)d;
+                const double d = lam[S - 1][i] - lam[1][i];
+                g = w5<double>(i) * cb * d;
                 rsrc[1] += kap * d;
             }
             if (own) a.acc[4 * t + i - 1] += g;
         }
     }
     // (R Col)^T: nu_j = (1 - omega) lam_j + omega sum_i e_i lam_i + rsrc
-    const Real uu = Real(1.5) * (u * u + v * v);
-    Real e[5];
-    e[0] = w5<Real>(0) * (Real(1) - uu);
-    e[DE] = w5<Real>(DE) * (Real(1) + Real(3) * u + Real(4.5) * u * u - uu);
-    e[DN] = w5<Real>(DN) * (Real(1) + Real(3) * v + Real(4.5) * v * v - uu);
-    e[DW] = w5<Real>(DW) * (Real(1) - Real(3) * u + Real(4.5) * u * u - uu);
-    e[DS] = w5<Real>(DS) * (Real(1) - Real(3) * v + Real(4.5) * v * v - uu);
-    const Real keep = Real(1) - a.omega;
+    const double u = (double)u_, v = (double)v_, uu = 1.5 * (u * u + v * v);
+    double e[5];
+    e[0] = w5<double>(0) * (1.0 - uu);
+    e[DE] = w5<double>(DE) * (1.0 + 3.0 * u + 4.5 * u * u - uu);
+    e[DN] = w5<double>(DN) * (1.0 + 3.0 * v + 4.5 * v * v - uu);
+    e[DW] = w5<double>(DW) * (1.0 - 3.0 * u + 4.5 * u * u - uu);
+    e[DS] = w5<double>(DS) * (1.0 - 3.0 * v + 4.5 * v * v - uu);
+    const double keep = 1.0 - a.omega;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        const Real M = e[0] * lam[s][0] + e[1] * lam[s][1] + e[2] * lam[s][2] + e[3] * lam[s][3] +
-                       e[4] * lam[s][4];
-        const Real add = a.omega * M + rsrc[s];
+        const double M = e[0] * lam[s][0] + e[1] * lam[s][1] + e[2] * lam[s][2] +
+                         e[3] * lam[s][3] + e[4] * lam[s][4];
+        const double add = a.omega * M + rsrc[s];
 #pragma unroll
-        for (int i = 0; i < 5; ++i) out[s][i] = keep * lam[s][i] + add;
+        for (int i = 0; i < 5; ++i) out[s][i] = Real(keep * lam[s][i] + add);
     }
 }
 
@@ -358,7 +363,7 @@ AdjArgs<Real> adj_args(Ctx *c, const void *nu_src, void *nu_dst, const void *tra
     a.ny = c->p.ny;
     a.nxp = c->nxp;
     a.plane = c->plane;
-    a.omega = Real(1.0 / c->p.tau_g);
+    a.omega = 1.0 / c->p.tau_g;
     a.L = c->L;
     return a;
 }
