@@ -266,6 +266,29 @@ int lbf_version(void);
 lbf_status lbf_probe_copy(const void *src_dev, void *dst_dev, size_t nbytes, void *hip_stream,
                           double *ms);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc) and hold no
+ * context: the outlet fluxes N[0..nspecies), the inflow of A and eps of an
+ * ADR state blob, as lbf_efficiency returns them for the context the blob
+ * came from.  p: the lattice's parameters (nx, ny, real_bytes, nspecies,
+ * c_in, flux_col, flags bit 2 are used; the rest is validated as by
+ * lbf_create).  state_dev: device blob as lbf_get_state writes it (two
+ * lattices and the header; caller-owned, read only).  node_type_dev: device
+ * uint8 [ny][nx] of the same lattice (0 = fluid).  hip_stream: the stream to
+ * use; the current device must be the stream's.  Output pointers are host
+ * memory and may be NULL.  The library's scratch for the reduction is a
+ * file-scope device array of 128 KiB + 32 B on each GPU it runs on (kept
+ * until the process ends): no hipMalloc, hipFree or allocating library call.
+ * Lattices of more than 262144 rows exceed it: LBF_ENOMEM.  LBF_EINVAL for
+ * bad parameters, a periodic box or a blob whose header does not match p;
+ * LBF_ESTATE for a blob with no step taken; LBF_EDIVERGED for non-finite
+ * fluxes.  Calls on one GPU share its scratch and overlapping calls race:
+ * serialise them (one stream, or synchronisation between streams).
+ * Synchronises the stream. */
+lbf_status lbf_efficiency_noalloc(const lbf_params *p, const void *state_dev,
+                                  const uint8_t *node_type_dev, void *hip_stream, double *eps,
+                                  double *N, double *inflow_A);
+
 /* ---- batched Pe x Da sweep --------------------------------------------- *
  * n independent instances (own geometry, size, tau_g, vel_scale, rates) run
  * together: one kernel launch per time step covers the tiles of every active

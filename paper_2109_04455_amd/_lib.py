@@ -81,6 +81,7 @@ SIGNATURES = {
     "lbf_get_state": (_I, [_P, _P]),
     "lbf_set_state": (_I, [_P, _P]),
     "lbf_prepare_adr_steps": (_I, [_P, _L]),
+    "lbf_efficiency_noalloc": (_I, [_PP, _P, _P, _P, _PD, _PD, _PD]),
     "lbf_time_adr_steps": (_I, [_P, _L, _PD]),
     "lbf_time_flow_steps": (_I, [_P, _L, _PD]),
     "lbf_status_str": (ctypes.c_char_p, [_I]),

@@ -175,3 +175,20 @@ def test_unshifted_a_with_fp32_arithmetic_rejected(L):
     st, msg = _create(L, _params(L, flags=4 | 16, real_bytes=8))
     assert st == 0, msg
 
+
+def test_noalloc_efficiency_rejects_before_any_device_work(L):
+    # host-side checks of the allocation-free entry point: bad parameters,
+    # NULL inputs and lattices taller than its scratch (262144 rows)
+    p = _params(L, nx=8, ny=300000)
+    d = ctypes.c_double()
+    assert L.lbf_efficiency_noalloc(ctypes.byref(p), ctypes.c_void_p(16), ctypes.c_void_p(16),
+                                    None, ctypes.byref(d), None, None) == -2
+    p = _params(L)
+    assert L.lbf_efficiency_noalloc(ctypes.byref(p), None, ctypes.c_void_p(16), None,
+                                    ctypes.byref(d), None, None) == -1
+    p = _params(L, boundary=1)
+    assert L.lbf_efficiency_noalloc(ctypes.byref(p), ctypes.c_void_p(16), ctypes.c_void_p(16),
+                                    None, ctypes.byref(d), None, None) == -1
+    p = _params(L, tau_g=0.4)
+    assert L.lbf_efficiency_noalloc(ctypes.byref(p), ctypes.c_void_p(16), ctypes.c_void_p(16),
+                                    None, ctypes.byref(d), None, None) == -1
