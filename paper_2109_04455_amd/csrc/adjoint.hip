@@ -56,32 +56,34 @@ struct AdjArgs {
 
 // The gather of one adjoint step at node x: lam(m) from nu(m+1).  blk_of(s)
 // addresses species s's 5 planes with byte offsets: PB between planes, RB
-// between rows, o the node's own.
+// between rows, o the node's own.  Sources are chosen by offset and all
+// loads are issued before any arithmetic (no wait per direction).
 template <typename Real, int S, typename BlkOf, typename Off>
 __device__ __forceinline__ void adj_gather(const BlkOf &blk_of, Off PB, Off RB, Off o, int x,
                                            int nx, unsigned m, Real (&lam)[S][5])
 {
     constexpr Off B = sizeof(Real);
     const Off oE = o + DE * PB, oN = o + DN * PB, oW = o + DW * PB, oS = o + DS * PB;
+    const bool in = x == 0, out = x == nx - 1;
+    // z_E(x) feeds g_E(x+1), or g_W(x) by bounce-back, or the outlet rule;
+    // z_W(x) feeds g_W(x-1), or g_E(x) by bounce-back / the inlet rule
+    const Off src[5] = {o, (out || (m & BIT_E)) ? oW : oE + B, (m & BIT_N) ? oS : oN + RB,
+                        (in || (m & BIT_W)) ? oE : oW - B, (m & BIT_S) ? oN : oS - RB};
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const auto nu = blk_of(s);
-        lam[s][0] = nu.load(o);
-        // z_E(x) feeds g_E(x+1), or g_W(x) by bounce-back, or the outlet rule
-        if (x == nx - 1)
-            lam[s][DE] = -nu.load(oW);
-        else
-            lam[s][DE] = nu.load((m & BIT_E) ? oW : oE + B);
-        lam[s][DN] = nu.load((m & BIT_N) ? oS : oN + RB);
-        // z_W(x) feeds g_W(x-1), or g_E(x) by bounce-back / the inlet rule
-        if (x == 0)
-            lam[s][DW] = s == 0 ? -nu.load(oE) : nu.load(oE);
-        else
-            lam[s][DW] = nu.load((m & BIT_W) ? oE : oW - B);
-        lam[s][DS] = nu.load((m & BIT_S) ? oN : oS - RB);
-        if (x == nx - 1) {
-            // outlet: every post-collision population enters C_b of g_W
-            const Real ow = Real(2) * w5<Real>(DW) * nu.load(oW);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) lam[s][i] = nu.load(src[i]);
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        if (in && s == 0) lam[s][DW] = -lam[s][DW];
+        if (out) {
+            // lam[s][DE] holds nu_W(x) here.  Outlet: every post-collision
+            // population enters C_b of g_W
+            const Real nw = lam[s][DE];
+            lam[s][DE] = -nw;
+            const Real ow = Real(2) * w5<Real>(DW) * nw;
 #pragma unroll
             for (int i = 0; i < 5; ++i) lam[s][i] += ow;
         }
@@ -107,14 +109,24 @@ __device__ __forceinline__ void adj_local(const AdjArgs<Real> &a, const Real *tr
     if (m & 0xF0u) {
         const int off[5] = {0, 1, a.nxp, -1, -a.nxp};
         const int t = a.trace_idx[id];
+        // rate and type of the four neighbours loaded together (index
+        // clamped into the plane), used where a link bit is set
+        Real kv[5];
+        uint8_t tv[5];
+#pragma unroll
+        for (int i = 1; i < 5; ++i) {
+            const long j = (long)id + off[i];
+            const size_t sid = (size_t)(j < 0 ? 0 : (j >= (long)a.plane ? (long)a.plane - 1 : j));
+            kv[i] = a.kr[sid];
+            tv[i] = a.type[sid];
+        }
         const double ca = (double)trace[2 * t], cb = (double)trace[2 * t + 1];
 #pragma unroll
         for (int i = 1; i < 5; ++i) {
             if (!((m >> (3 + i)) & 1u)) continue;
-            const size_t sid = id + off[i];
-            const double kap = (double)a.kr[sid] * w5<double>(i);
+            const double kap = (double)kv[i] * w5<double>(i);
             double g;
-            if (a.type[sid] == 2) {
+            if (tv[i] == 2) {
                 const double d = lam[1][i] - lam[0][i];
                 g = w5<double>(i) * ca * d;
                 rsrc[0] += kap * d;

@@ -30,31 +30,38 @@ __device__ __forceinline__ T w5(int i)
 // bytes after the block base, rows are RB bytes apart and the node itself is
 // at byte offset o.  A choice between two sources (bounce-back or
 // neighbour) is a choice of offset.  Blk: PopBlock (lattice in HBM) or
-// LdsBlock (a tile in LDS).
+// LdsBlock (a tile in LDS).  The five loads are issued together with
+// offsets chosen by selects, and converted to Acc only after all of them:
+// a branch per direction with the conversion inside would wait for each
+// load in turn.  Inlet (x = 0): E comes from the node's own W (with the
+// Dirichlet value for species A); outlet (x = nx - 1): W from the node's
+// own populations (three more loads, outlet nodes only).
 template <typename Acc, typename Blk, typename Off>
 __device__ __forceinline__ void pull5_at(const Blk &blk, Off PB, Off RB, Off o, int x, int nx,
                                          unsigned m, bool species_a, Acc inlet_e, Acc (&h)[5])
 {
-    constexpr Off B = sizeof(typename Blk::real_type);
-    auto at = [&](Off off) { return Acc(blk.load(off)); };
+    using R = typename Blk::real_type;
+    constexpr Off B = sizeof(R);
     const Off oE = o + DE * PB, oN = o + DN * PB, oW = o + DW * PB, oS = o + DS * PB;
-    h[0] = at(o);
-    // E arrives from x - 1
-    if (x == 0)
-        h[DE] = species_a ? inlet_e - at(oW) : at(oW);
-    else
-        h[DE] = at((m & BIT_W) ? oW : oE - B);
-    // N arrives from y - 1
-    h[DN] = at((m & BIT_S) ? oS : oN - RB);
-    // W arrives from x + 1
-    if (x == nx - 1) {
-        const Acc sum = at(o) + at(oE) + at(oN) + at(oW) + at(oS);
-        h[DW] = Acc(2) * w5<Acc>(DW) * sum - at(oE);
-    } else {
-        h[DW] = at((m & BIT_E) ? oE : oW + B);
+    const bool in = x == 0, out = x == nx - 1;
+    // E arrives from x - 1, N from y - 1, W from x + 1, S from y + 1
+    const Off sE = (in || (m & BIT_W)) ? oW : oE - B;
+    const Off sN = (m & BIT_S) ? oS : oN - RB;
+    const Off sW = (out || (m & BIT_E)) ? oE : oW + B;
+    const Off sS = (m & BIT_N) ? oN : oS + RB;
+    const R r0 = blk.load(o), rE = blk.load(sE), rN = blk.load(sN), rW = blk.load(sW),
+            rS = blk.load(sS);
+    h[0] = Acc(r0);
+    h[DE] = Acc(rE);
+    h[DN] = Acc(rN);
+    h[DW] = Acc(rW);
+    h[DS] = Acc(rS);
+    if (in && species_a) h[DE] = inlet_e - h[DE];
+    if (out) {
+        // rW is the node's own E here
+        const Acc sum = h[0] + h[DW] + Acc(blk.load(oN)) + Acc(blk.load(oW)) + Acc(blk.load(oS));
+        h[DW] = Acc(2) * w5<Acc>(DW) * sum - h[DW];
     }
-    // S arrives from y + 1
-    h[DS] = at((m & BIT_N) ? oN : oS + RB);
 }
 
 // The same from the lattice in HBM: `src` is the base of this species, P the
@@ -71,17 +78,75 @@ __device__ __forceinline__ void pull5(const Real *__restrict__ src, size_t P, si
     pull5_at<Acc>(blk, PB, (Off)nxp * B, (Off)id * B, x, nx, m, species_a, inlet_e, h);
 }
 
+// Gather of all S species at one node: the source offsets are chosen once
+// (they are the same for every species) and all 5 S loads are issued before
+// any is converted to Acc, so a wavefront waits for memory once per gather.
+// blk_of(s): the block of species s (PopBlock or LdsBlock).  Same results
+// as pull5_at per species.
+template <typename Acc, int S, typename BlkOf, typename Off>
+__device__ __forceinline__ void pullS_at(const BlkOf &blk_of, Off PB, Off RB, Off o, int x,
+                                         int nx, unsigned m, Acc inlet_e, Acc (&h)[S][5])
+{
+    using BlkT = decltype(blk_of(0));
+    using R = typename BlkT::real_type;
+    constexpr Off B = sizeof(R);
+    const Off oE = o + DE * PB, oN = o + DN * PB, oW = o + DW * PB, oS = o + DS * PB;
+    const bool in = x == 0, out = x == nx - 1;
+    const Off src[5] = {o, (in || (m & BIT_W)) ? oW : oE - B, (m & BIT_S) ? oS : oN - RB,
+                        (out || (m & BIT_E)) ? oE : oW + B, (m & BIT_N) ? oN : oS + RB};
+    R r[S][5];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const BlkT blk = blk_of(s);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) r[s][i] = blk.load(src[i]);
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) h[s][i] = Acc(r[s][i]);
+    if (in) h[0][DE] = inlet_e - h[0][DE];
+    if (out) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            // h[s][DW] is the node's own E here
+            const BlkT blk = blk_of(s);
+            const Acc sum = h[s][0] + h[s][DW] + Acc(blk.load(oN)) + Acc(blk.load(oW)) +
+                            Acc(blk.load(oS));
+            h[s][DW] = Acc(2) * w5<Acc>(DW) * sum - h[s][DW];
+        }
+    }
+}
+
+// The same from the lattice in HBM: species s starts at src + s 5 P.
+template <typename Real, typename Acc, int S, bool NT, bool WIDE>
+__device__ __forceinline__ void pullS(const Real *__restrict__ src, size_t P, size_t id, int x,
+                                      int nx, int nxp, unsigned m, Acc inlet_e, Acc (&h)[S][5])
+{
+    using Off = off_t_<WIDE>;
+    constexpr Off B = sizeof(Real);
+    const Off PB = (Off)P * B;
+    const auto blk_of = [&](int s) { return PopBlock<Real, NT, WIDE>(src + (size_t)s * 5 * P, 5 * PB); };
+    pullS_at<Acc, S>(blk_of, PB, (Off)nxp * B, (Off)id * B, x, nx, m, inlet_e, h);
+}
+
 // Gather for a box periodic in x and y (no inlet or outlet); solid
 // neighbours still bounce back.  nb[d] are the wrapped neighbour indices.
 template <typename Real, typename Acc, bool NT>
 __device__ __forceinline__ void pull5_periodic(const Real *__restrict__ src, size_t P, size_t id,
                                                const size_t (&nb)[5], unsigned m, Acc (&h)[5])
 {
-    h[0] = Acc(ld<NT>(src + id));
-    h[DE] = Acc((m & BIT_W) ? ld<NT>(src + DW * P + id) : ld<NT>(src + DE * P + nb[DW]));
-    h[DN] = Acc((m & BIT_S) ? ld<NT>(src + DS * P + id) : ld<NT>(src + DN * P + nb[DS]));
-    h[DW] = Acc((m & BIT_E) ? ld<NT>(src + DE * P + id) : ld<NT>(src + DW * P + nb[DE]));
-    h[DS] = Acc((m & BIT_N) ? ld<NT>(src + DN * P + id) : ld<NT>(src + DS * P + nb[DN]));
+    // sources chosen by address, all five loads issued before any use
+    const Real r0 = ld<NT>(src + id);
+    const Real rE = ld<NT>((m & BIT_W) ? src + DW * P + id : src + DE * P + nb[DW]);
+    const Real rN = ld<NT>((m & BIT_S) ? src + DS * P + id : src + DN * P + nb[DS]);
+    const Real rW = ld<NT>((m & BIT_E) ? src + DE * P + id : src + DW * P + nb[DE]);
+    const Real rS = ld<NT>((m & BIT_N) ? src + DN * P + id : src + DS * P + nb[DN]);
+    h[0] = Acc(r0);
+    h[DE] = Acc(rE);
+    h[DN] = Acc(rN);
+    h[DW] = Acc(rW);
+    h[DS] = Acc(rS);
 }
 
 // Neighbour indices x + c_d of node (x, y), wrapped in x and y.
@@ -134,40 +199,66 @@ template <typename Real, typename Acc, int S, bool TRACE, int MODE = 0>
 __device__ __forceinline__ void collide_react(const AdrArgs<Real> &a, size_t id, unsigned m, Acc u,
                                               Acc v, Acc (&h)[S][5], const size_t *nb = nullptr)
 {
+    // FP64: h* = (1 - omega) h + omega feq with the per-node factors
+    // mul = omega w (1 + p), off = omega w p cref (two operations per
+    // population).  FP32 arithmetic keeps h - omega (h - feq) with
+    // mul = w (1 + p): 1 + p_i together loses less of the small p_i.
+    constexpr bool F64 = sizeof(Acc) == 8;
+    const Acc om = Acc(a.omega);
     Acc mul[5], off[5];
     {
         Acc p[5];
         eq_factors(u, v, p);
+        const Acc omc = om * Acc(a.cref);
 #pragma unroll
         for (int i = 0; i < 5; ++i) {
             const Acc w = w5<Acc>(i), wp = w * p[i];
-            // FP32 arithmetic keeps 1 + p_i together: w + w p_i loses more of
-            // the small p_i in single precision
-            mul[i] = sizeof(Acc) == 4 ? w * (Acc(1) + p[i]) : w + wp;
-            off[i] = wp * Acc(a.cref);
+            if constexpr (F64) {
+                mul[i] = om * w + om * wp;
+                off[i] = omc * wp;
+            } else {
+                mul[i] = w * (Acc(1) + p[i]);
+                off[i] = wp * Acc(a.cref);
+            }
         }
     }
+    const Acc keep = Acc(1) - om;
     Acc c[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const Acc delta = h[s][0] + h[s][1] + h[s][2] + h[s][3] + h[s][4];
         c[s] = (s == 0 ? Acc(a.cref) : Acc(0)) + delta;
-        if (s == 0)
-            collide5<Acc, true>(h[s], delta, mul, off, Acc(a.omega));
-        else
-            collide5<Acc, false>(h[s], delta, mul, off, Acc(a.omega));
+        if constexpr (F64) {
+#pragma unroll
+            for (int i = 0; i < 5; ++i)
+                h[s][i] = keep * h[s][i] + (s == 0 ? mul[i] * delta + off[i] : mul[i] * delta);
+        } else if (s == 0) {
+            collide5<Acc, true>(h[s], delta, mul, off, om);
+        } else {
+            collide5<Acc, false>(h[s], delta, mul, off, om);
+        }
     }
     if (m & 0xF0u) {
         const int off[5] = {0, 1, a.nxp, -1, -a.nxp};
         if (MODE == 0) {
             // Eq. source_lbm at the links: the population heading into a
-            // catalytic node loses k w_i C_src, the product gains it
+            // catalytic node loses k w_i C_src, the product gains it.  The
+            // rate and type of all four neighbours are loaded together (the
+            // index clamped into the plane), then used where a link bit is set
+            Real kv[5];
+            uint8_t tv[5];
+#pragma unroll
+            for (int i = 1; i < 5; ++i) {
+                const long j = (long)id + off[i];
+                const size_t sid = nb ? nb[i] : (size_t)(j < 0 ? 0 : (j >= (long)a.plane ? (long)a.plane - 1 : j));
+                kv[i] = a.kr[sid];
+                tv[i] = a.type[sid];
+            }
 #pragma unroll
             for (int i = 1; i < 5; ++i) {
                 if (!((m >> (3 + i)) & 1u)) continue;
-                const size_t sid = nb ? nb[i] : id + off[i];
-                const Acc k = Acc(a.kr[sid]);
-                if (a.type[sid] == 2) {
+                const Acc k = Acc(kv[i]);
+                if (tv[i] == 2) {
                     const Acc r = k * w5<Acc>(i) * c[0];
                     h[0][i] -= r;
                     h[1][i] += r;
@@ -246,10 +337,7 @@ __device__ __forceinline__ void node_update(const AdrArgs<Real> &a, int x, int y
     const size_t P = a.plane;
     const Acc inlet_e = Acc(2) * w5<Acc>(DE) * (Acc(a.cin) - Acc(a.cref));
     Acc h[S][5];
-#pragma unroll
-    for (int s = 0; s < S; ++s)
-        pull5<Real, Acc, NT, WIDE>(a.src + (size_t)s * 5 * P, P, id, x, a.nx, a.nxp, m, s == 0,
-                                   inlet_e, h[s]);
+    pullS<Real, Acc, S, NT, WIDE>(a.src, P, id, x, a.nx, a.nxp, m, inlet_e, h);
     collide_react_store<Real, Acc, S, TRACE, NT, WIDE>(a, id, m, h);
 }
 
@@ -274,10 +362,7 @@ __device__ __forceinline__ void node_update_ext(const AdrArgs<Real> &a, int x, i
 #pragma unroll
         for (int d = 0; d < 5; ++d) nb[d] = id + off[d];
         const double inlet_e = 2.0 * w5<double>(DE) * (a.cin - a.cref);
-#pragma unroll
-        for (int s = 0; s < S; ++s)
-            pull5<Real, double, NT, true>(a.src + (size_t)s * 5 * P, P, id, x, a.nx, a.nxp, m,
-                                          s == 0, inlet_e, h[s]);
+        pullS<Real, double, S, NT, true>(a.src, P, id, x, a.nx, a.nxp, m, inlet_e, h);
     }
     collide_react<Real, double, S, false, MODE>(a, id, m, double(a.ua[id]), double(a.ua[P + id]),
                                                 h, nb);
@@ -375,22 +460,25 @@ __device__ __forceinline__ void pair_step1(PairLds<Real, S> &L, const AdrArgs<Re
 {
     constexpr int EY = PairTile<Real>::EY, TY = EY - 2, EP = PairLds<Real, S>::EP;
     if (!n.inside) return;
-    if (PairLds<Real, S>::ULDS) {
-        L.mask[n.e] = (uint8_t)q.m;
-        L.vel[n.e] = q.u;
-        L.vel[EP + n.e] = q.v;
-    }
+    const size_t P = a.plane;
+    if (PairLds<Real, S>::ULDS) L.mask[n.e] = (uint8_t)q.m;
     // solid nodes gather nothing: their mask has no bounce-back bits, so a
     // gather would read the neighbours' planes (past the last row of the
     // lattice for a node of the top wall row)
-    if (q.m == MASK5_SOLID) return;
-    const size_t P = a.plane;
+    if (q.m == MASK5_SOLID) {
+        if (PairLds<Real, S>::ULDS) {
+            L.vel[n.e] = q.u;
+            L.vel[EP + n.e] = q.v;
+        }
+        return;
+    }
     const Acc inlet_e = Acc(2) * w5<Acc>(DE) * (Acc(a.cin) - Acc(a.cref));
     Acc h[S][5];
-#pragma unroll
-    for (int s = 0; s < S; ++s)
-        pull5<Real, Acc, PairTile<Real>::NTL, WIDE>(a.src + (size_t)s * 5 * P, P, n.id, n.x, a.nx,
-                                                    a.nxp, q.m, s == 0, inlet_e, h[s]);
+    pullS<Real, Acc, S, PairTile<Real>::NTL, WIDE>(a.src, P, n.id, n.x, a.nx, a.nxp, q.m, inlet_e, h);
+    if (PairLds<Real, S>::ULDS) {
+        L.vel[n.e] = q.u;
+        L.vel[EP + n.e] = q.v;
+    }
     if constexpr (TRACE) {
         // step-1 concentrations are recorded by the block owning the node
         AdrArgs<Real> a1 = a;
@@ -428,10 +516,9 @@ __device__ __forceinline__ bool pair_step2(const PairLds<Real, S> &L, const AdrA
     if (m == MASK5_SOLID) return false;
     constexpr uint32_t LB = sizeof(Real);
     const Acc inlet_e = Acc(2) * w5<Acc>(DE) * (Acc(a.cin) - Acc(a.cref));
-#pragma unroll
-    for (int s = 0; s < S; ++s)
-        pull5_at<Acc>(LdsBlock<Real>{L.pop + s * 5 * EP}, (uint32_t)(EP * LB), (uint32_t)(EX * LB),
-                      (uint32_t)e * LB, x, a.nx, m, s == 0, inlet_e, h[s]);
+    const auto blk_of = [&](int s) { return LdsBlock<Real>{L.pop + s * 5 * EP}; };
+    pullS_at<Acc, S>(blk_of, (uint32_t)(EP * LB), (uint32_t)(EX * LB), (uint32_t)e * LB, x, a.nx, m,
+                     inlet_e, h);
     Acc u, v;
     if (ULDS) {
         u = Acc(L.vel[e]);

@@ -11,10 +11,9 @@ namespace lbf {
 // 8 XCDs round-robin (block h runs on XCD h mod 8); with xcd_remap the
 // blocks of XCD j are given one contiguous range of tiles, so tiles that
 // share halo cache lines mostly run under the same L2.
-__device__ __forceinline__ void tile_of_block(const Launch &L, int &bx, int &by)
+__device__ __forceinline__ void tile_of_index(const Launch &L, int h, int &bx, int &by)
 {
     const int nb = L.gx * L.gy;
-    const int h = blockIdx.x;
     int logical = h;
     if (L.xcd_remap) {
         const int q = nb >> 3, r = nb & 7, j = h & 7, k = h >> 3;
@@ -22,6 +21,11 @@ __device__ __forceinline__ void tile_of_block(const Launch &L, int &bx, int &by)
     }
     bx = logical % L.gx;
     by = logical / L.gx;
+}
+
+__device__ __forceinline__ void tile_of_block(const Launch &L, int &bx, int &by)
+{
+    tile_of_index(L, (int)blockIdx.x, bx, by);
 }
 
 __device__ __forceinline__ void tile_coords(const Launch &L, int &x, int &y)
