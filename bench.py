@@ -251,12 +251,24 @@ def _field_err(ca, cb):
     return max(errs), errs
 
 
+STEADY_CHUNK = 100_000
+
+
 def run_to_steady(c, max_steps=2_000_000, tol=STEADY_TOL, check_every=1000):
-    """Continue an ADR run until a check is steady; returns a summary."""
+    """Continue an ADR run until a check is steady; returns a summary.  The
+    run goes in calls of STEADY_CHUNK steps with a progress line after each;
+    the library's steady-state test starts afresh at each call (its first
+    check has no previous eps), so the stop step can be one check later than
+    that of a single call."""
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    n, conv = c.adr_run(max_steps, check_every=check_every, tol=tol)
+    n, conv = 0, False
+    while n < max_steps and not conv:
+        k, conv = c.adr_run(min(STEADY_CHUNK, max_steps - n), check_every=check_every, tol=tol)
+        n += k
+        log(f"  {int(c.adr_steps())} ADR steps, eps {c.efficiency()[0]:.6e}" +
+            (" (steady)" if conv else ""))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     eps, N, inflow = c.efficiency()
@@ -281,6 +293,7 @@ def steady_pair(w, flow_max=600_000, adr_max=2_000_000, keep=False):
     torch.cuda.synchronize()
     out["flow"] = {"steps": fsteps, "residual_over_u0": fres / w.u0, "converged": fconv,
                    "seconds": round(time.perf_counter() - t0, 2)}
+    log(f"  {w.name}: flow {fsteps} steps; ADR to steady (FP32)")
     c32.adr_init()
     out["fp32"] = run_to_steady(c32, adr_max)
     c64 = _ctx(w, "f64")
@@ -293,7 +306,10 @@ def steady_pair(w, flow_max=600_000, adr_max=2_000_000, keep=False):
     c64.adr_init()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    c64.adr_run(out["fp32"]["steps"], check_every=1000, tol=0)
+    while c64.adr_steps() < out["fp32"]["steps"]:
+        c64.adr_run(min(STEADY_CHUNK, out["fp32"]["steps"] - int(c64.adr_steps())),
+                    check_every=1000, tol=0)
+        log(f"  FP64: {int(c64.adr_steps())} of {out['fp32']['steps']} ADR steps")
     torch.cuda.synchronize()
     e64, N64, in64 = c64.efficiency()
     out["fp64"] = {"steps": int(c64.adr_steps()), "eps": e64, "N": [float(v) for v in N64],
@@ -373,10 +389,15 @@ def c2_pe_sweep_leg(pes=(1.0, 10.0, 100.0, 1000.0)):
     paper's range to its steady state, FP32 against FP64 (opt-in: several
     minutes)."""
     from workloads import make_workload
+    import paper_2109_04455_amd as L
     out = {}
     for pe in pes:
         log(f"C2 at Pe {pe:g}")
-        out[str(pe)] = steady_pair(make_workload("C2", pe=pe))
+        try:
+            out[str(pe)] = steady_pair(make_workload("C2", pe=pe))
+        except L.LbfError as e:
+            # e.g. LBF_EDIVERGED at the stability edge: recorded, not fatal
+            out[str(pe)] = {"error": str(e)}
     return out
 
 
@@ -402,10 +423,13 @@ def batch_leg(steps=2000, flow_steps=2000, cpu=True, tts_steps=0, tts_tol=STEADY
     same = bool((b["product_flux"] == s["product_flux"]).all())
     tts = None
     if tts_steps > 0:
+        log(f"  sweep to convergence (at most {tts_steps} ADR steps): batched")
         bt = sweep_batched(ws, tts_flow_steps, tts_steps, check_every=1000, tol=tts_tol,
                            flow_tol=tts_flow_tol, tile=tile, flags=flags)
+        log(f"  serial ({bt['seconds']:.1f} s batched)")
         st = sweep_serial(ws, tts_flow_steps, tts_steps, check_every=1000, tol=tts_tol,
                           flow_tol=tts_flow_tol)
+        log(f"  FP64 batched ({st['seconds']:.1f} s serial)")
         w64 = [dataclasses.replace(w, real="f64") for w in ws]
         b64 = sweep_batched(w64, tts_flow_steps, tts_steps, check_every=1000, tol=tts_tol,
                             flow_tol=tts_flow_tol, tile=tile, flags=flags)
@@ -682,8 +706,9 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--batch-tts-steps", type=int, default=0,
                     help="also run the sweep to convergence, capped at this many ADR steps")
-    ap.add_argument("--pe-sweep", action="store_true",
-                    help="also run C2 at Pe 1, 10, 100, 1000 to steady state, FP32 and FP64")
+    ap.add_argument("--pe-sweep", nargs="?", const="1,10,100,1000", default=None,
+                    help="also run C2 to steady state, FP32 and FP64, at these Pe "
+                         "(comma-separated; default 1,10,100,1000)")
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--no-noflow", action="store_true")
     ap.add_argument("--no-rwpt", action="store_true")
@@ -826,7 +851,7 @@ def main():
         out["c1_steady_and_adjoint"] = c1_and_adjoint_leg(args.adjoint_steps)
     if args.pe_sweep:
         log("C2 Pe sweep to steady state")
-        out["c2_pe_sweep"] = c2_pe_sweep_leg()
+        out["c2_pe_sweep"] = c2_pe_sweep_leg(tuple(float(v) for v in args.pe_sweep.split(",")))
     if not args.no_batch:
         log("batched sweep")
         out["batched_sweep"] = batch_leg(args.batch_steps, cpu=not args.no_cpu_baseline,

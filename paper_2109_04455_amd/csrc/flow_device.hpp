@@ -156,8 +156,12 @@ __device__ __forceinline__ void node_update(const FlowArgs<Real> &a, int x, int 
 // Nodes (x, y) and (x, y + 1) in one thread: the loads of both are issued
 // before either is collided, which hides the latency of the FP64 collision
 // (two rows per thread: 73 -> 54 us per step on a 4096 x 1024 lattice; FP32
-// arithmetic gains nothing).  A node that is solid or outside the lattice
-// loads its own slots and stores nothing.
+// arithmetic gains nothing).  The loads go out with the masks, not after
+// them: every population is first read from its streaming source (the
+// node's own slot where that source lies outside the lattice), and only
+// nodes next to a wall read their bounce-back populations afterwards, so
+// wavefronts away from walls wait for memory once.  A node that is solid or
+// outside the lattice stores nothing.
 template <typename Real, typename Acc, bool WRITE_U, bool NT, bool WIDE>
 __device__ __forceinline__ void node_update2(const FlowArgs<Real> &a, int x, int y)
 {
@@ -165,26 +169,43 @@ __device__ __forceinline__ void node_update2(const FlowArgs<Real> &a, int x, int
     constexpr Off B = sizeof(Real);
     const Off PB = (Off)a.plane * B;
     const PopBlock<Real, NT, WIDE> in(a.src, 9 * PB);
-    bool live[2];
+    bool valid[2];
     size_t ids[2];
-    Acc h[2][9];
+    unsigned m[2];
+    Real r[2][9];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-        ids[k] = (size_t)(y + k < a.ny ? y + k : y) * a.nxp + x;
-        const unsigned m = a.mask9[ids[k]];
-        live[k] = y + k < a.ny && !(m & MASK9_SOLID);
+        const int yk = y + k;
+        valid[k] = yk < a.ny;
+        ids[k] = (size_t)(valid[k] ? yk : y) * a.nxp + x;
+        m[k] = a.mask9[ids[k]];
         const Off o = (Off)ids[k] * B;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            bool open;
-            const Off off = source_off<Off>(i, x, a.nx, a.nxp, m, o, PB, B, open);
-            const Acc v = Acc(in.load(live[k] ? off : o + i * PB));
-            h[k][i] = open ? Acc(0) : v;
+            const int sx = x - CX[i], sy = yk - CY[i];
+            const bool inside = valid[k] && sx >= 0 && sx < a.nx && sy >= 0 && sy < a.ny;
+            const Off back = (Off)(ptrdiff_t)(CX[i] + CY[i] * a.nxp) * B;  // modular
+            r[k][i] = in.load(inside ? o + i * PB - back : o + i * PB);
         }
     }
 #pragma unroll
-    for (int k = 0; k < 2; ++k)
-        if (live[k]) finish_node<Real, Acc, WRITE_U, NT, WIDE>(a, x, y + k, ids[k], h[k]);
+    for (int k = 0; k < 2; ++k) {
+        if (!valid[k] || (m[k] & MASK9_SOLID)) continue;
+        const Off o = (Off)ids[k] * B;
+        if (m[k] & 0xFFu) {
+            // half-way bounce-back: population i from the node's own opposite
+#pragma unroll
+            for (int i = 1; i < 9; ++i)
+                if ((m[k] >> (OPP[i] - 1)) & 1u) r[k][i] = in.load(o + OPP[i] * PB);
+        }
+        Acc h[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const int sx = x - CX[i];
+            h[i] = (sx < 0 || sx >= a.nx) ? Acc(0) : Acc(r[k][i]);
+        }
+        finish_node<Real, Acc, WRITE_U, NT, WIDE>(a, x, y + k, ids[k], h);
+    }
 }
 
 }  // namespace flow

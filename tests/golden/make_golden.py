@@ -19,7 +19,13 @@ the inflow, the total of each species over the fluid nodes, the maximum of
 each concentration field and the concentrations at 512 seeded fluid nodes
 plus each field's arg-max (the GPU test compares its fields there).
 
-    python tests/golden/make_golden.py [c0] [c2q]
+batch_conv.json -- four small two-membrane cascades of the batched sweep's
+generator (seed 11, 32 rows, 120 ... 200 columns, two fibres R = 5 per band,
+Pe in [2, 10], Da in [1, 10]): 3000 flow steps, then ADR steps until a check
+(every 1000 steps) is steady at tol 1e-7, at most 40,000.  Stored per
+instance: the stop step, eps, the outlet fluxes and the inflow.
+
+    python tests/golden/make_golden.py [c0] [c2q] [batch]
 """
 import json
 import os
@@ -87,6 +93,31 @@ def c2q(pe):
             "c_argmax": [[float(c[s][a[0], a[1]]) for a in arg] for s in range(w.nspecies)]}
 
 
+BATCH_CONV = {"n": 4, "seed": 11, "ny": 32, "nx_range": [120, 200], "fibres": 2, "r": 5,
+              "pe_range": [2.0, 10.0], "da_range": [1.0, 10.0]}
+BATCH_FLOW, BATCH_TOL, BATCH_BUDGET = 3000, 1e-7, 40000
+
+
+def batch_conv_one(i):
+    from workloads import batch_instances
+    kw = dict(BATCH_CONV)
+    kw["nx_range"], kw["pe_range"], kw["da_range"] = (tuple(kw["nx_range"]), tuple(kw["pe_range"]),
+                                                      tuple(kw["da_range"]))
+    w = batch_instances(**kw)[i]
+    ux, uy, _, _ = R.flow_steady(w.node_type, w.tau_f, w.u0, BATCH_FLOW, tol=0)
+    g, steps, flux, inflow, eps = R.adr_steady(w.node_type, w.k, ux, uy, w.nspecies, w.tau_g,
+                                               BATCH_BUDGET, 1000, BATCH_TOL, w.c_in, w.vel_scale)
+    return {"nx": w.nx, "pe": w.params.pe, "da": w.params.da, "tau_g": w.tau_g,
+            "adr_steps": steps, "eps": eps, "N": list(map(float, flux)), "inflow": inflow}
+
+
+def batch_conv():
+    with ProcessPoolExecutor(BATCH_CONV["n"]) as ex:
+        runs = list(ex.map(batch_conv_one, range(BATCH_CONV["n"])))
+    return {"instances": BATCH_CONV, "flow_steps": BATCH_FLOW, "tol": BATCH_TOL,
+            "check_every": 1000, "budget": BATCH_BUDGET, "runs": runs}
+
+
 def _write(name, out):
     with open(os.path.join(HERE, name), "w") as f:
         json.dump(out, f, indent=0)
@@ -94,7 +125,9 @@ def _write(name, out):
 
 
 if __name__ == "__main__":
-    which = set(sys.argv[1:]) or {"c0", "c2q"}
+    which = set(sys.argv[1:]) or {"c0", "c2q", "batch"}
+    if "batch" in which:
+        _write("batch_conv.json", batch_conv())
     if "c2q" in which:
         with ProcessPoolExecutor(len(C2Q_PE)) as ex:
             for pe, out in zip(C2Q_PE, ex.map(c2q, C2Q_PE)):

@@ -100,28 +100,39 @@ def test_batch_matches_oracle():
 
 
 def test_batch_convergence_drops_instances_and_keeps_their_state():
+    # four small cascades that reach the steady-state test at tol 1e-7 after
+    # different step counts (the oracle's stop steps and eps are stored in
+    # tests/golden/batch_conv.json): each instance leaves the tile table at
+    # the oracle's step, keeps its state while the others run on, and equals
+    # a single-lattice run of exactly its own step count
+    import json
+    import os
     import paper_2109_04455_amd as L
-    # moderate Pe so that most instances converge within the budget
-    ws = batch_instances(n=4, seed=11, ny=48, nx_range=(200, 400), fibres=2, r=8,
-                         pe_range=(0.5, 4.0), da_range=(1.0, 10.0))
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "batch_conv.json")))
+    kw = dict(ref["instances"])
+    for k in ("nx_range", "pe_range", "da_range"):
+        kw[k] = tuple(kw[k])
+    ws = batch_instances(**kw)
     b = L.Batch([_params(w, "f64") for w in ws])
     b.set_geometry([w.node_type for w in ws], [w.k for w in ws])
-    b.flow(400, check_every=400, tol=0)
-    budget = 150000
-    eps, prod, steps = b.run(budget, check_every=1000, tol=1e-5)
-    print("batch steps", steps.tolist(), flush=True)
-    assert (steps < budget).sum() >= 1
-    assert len(set(steps.tolist())) >= 2 or (steps < budget).all()
-    # each instance equals a single-lattice run of exactly its own step count
+    b.flow(ref["flow_steps"], check_every=ref["flow_steps"], tol=0)
+    eps, prod, steps = b.run(ref["budget"], check_every=ref["check_every"], tol=ref["tol"])
+    want = [r["adr_steps"] for r in ref["runs"]]
+    print("batch steps", steps.tolist(), "oracle", want, flush=True)
+    assert steps.tolist() == want
+    assert (steps < ref["budget"]).sum() >= 2 and len(set(want)) >= 2
     for i, w in enumerate(ws):
-        c = _single(w, 400, int(steps[i]), "f64")
+        r = ref["runs"][i]
+        c = _single(w, ref["flow_steps"], int(steps[i]), "f64")
         e1, N1, inflow = c.efficiency()
-        _agree("f64", 0, [b.concentration(i, 2)], [c.concentration(2)], (eps[i], prod[i]),
+        _agree("f64", 0, [b.concentration(i, s) for s in range(w.nspecies)],
+               [c.concentration(s) for s in range(w.nspecies)], (eps[i], prod[i]),
                (e1, N1[-1]), inflow)
-        if steps[i] < budget:
-            # converged (eps settled to 1e-5 per 1000 steps): what flows in
-            # leaves as A, B or C, up to the remaining transient
-            assert abs(N1.sum() - inflow) < 1e-2 * inflow
+        # converged: the product leaves and what flows in leaves as A, B or C
+        assert N1[-1] > 0 and abs(N1.sum() - inflow) <= 1e-6 * inflow
+        assert abs(eps[i] / r["eps"] - 1) <= 1e-9
+        assert np.abs(N1 - np.asarray(r["N"])).max() <= 1e-10 * inflow
+        c.close()
 
 
 def test_sweep_instances_full_size_short():
