@@ -424,15 +424,18 @@ def batch_leg(steps=2000, flow_steps=2000, cpu=True, tts_steps=0, tts_tol=STEADY
     tts = None
     if tts_steps > 0:
         log(f"  sweep to convergence (at most {tts_steps} ADR steps): batched")
+        prog = lambda n, a: log(f"    {n} ADR steps, {a} instances still running")  # noqa: E731
         bt = sweep_batched(ws, tts_flow_steps, tts_steps, check_every=1000, tol=tts_tol,
-                           flow_tol=tts_flow_tol, tile=tile, flags=flags)
+                           flow_tol=tts_flow_tol, tile=tile, flags=flags, chunk=50_000,
+                           progress=prog)
         log(f"  serial ({bt['seconds']:.1f} s batched)")
         st = sweep_serial(ws, tts_flow_steps, tts_steps, check_every=1000, tol=tts_tol,
                           flow_tol=tts_flow_tol)
         log(f"  FP64 batched ({st['seconds']:.1f} s serial)")
         w64 = [dataclasses.replace(w, real="f64") for w in ws]
         b64 = sweep_batched(w64, tts_flow_steps, tts_steps, check_every=1000, tol=tts_tol,
-                            flow_tol=tts_flow_tol, tile=tile, flags=flags)
+                            flow_tol=tts_flow_tol, tile=tile, flags=flags, chunk=50_000,
+                            progress=prog)
         same_steps = bt["steps"] == b64["steps"]
         ok = same_steps & (abs(b64["eps"]) > 0)
         rel = abs(bt["eps"][ok] / b64["eps"][ok] - 1)

@@ -305,12 +305,27 @@ lbf_status lbf_batch_set_geometry(lbf_batch b, const uint8_t *node_type_concat_d
 /* Flow for every instance: fixed max_steps when tol <= 0, else until each
  * instance meets the flow tolerance (converged instances stop stepping). */
 lbf_status lbf_batch_flow(lbf_batch b, long max_steps, int check_every, double tol);
-/* ADR for every instance from its initial state, converged instances are
- * dropped from the tile list.  tol <= 0: exactly max_steps for all.
- * Outputs (host arrays of n): eps, product flux (N of the last species),
- * steps taken. */
+/* ADR for every instance from its initial state (Sec. "Lattice-Boltzmann
+ * for Advection-Diffusion-Reaction", eps per Eq. A-B); every check_every
+ * steps of the run each active instance's steady-state test is applied
+ * (eps moved by at most tol of itself since its previous check, positive
+ * product outflux, outlet fluxes balancing the inflow of A within 1e-3) and
+ * converged instances are dropped from the tile list.  tol <= 0: exactly
+ * max_steps for all.  Outputs (host arrays of n): eps, product flux (N of
+ * the last species), steps taken by each instance.  LBF_ENOTCONV when
+ * tol > 0 and some instance is still active after max_steps (the outputs
+ * are written). */
 lbf_status lbf_batch_run(lbf_batch b, long max_steps, int check_every, double tol,
                          double *eps_host, double *product_flux_host, long *steps_host);
+/* Continue the current run by more_steps steps with the same active set and
+ * the same check schedule (checks every check_every steps counted from the
+ * start of the run; a call ending between two checks only observes): a run
+ * split into resumed calls whose lengths are multiples of check_every stops
+ * every instance at the same step as one call.  Outputs and LBF_ENOTCONV as
+ * for lbf_batch_run.  LBF_ESTATE when no run was started, or after
+ * lbf_batch_set_geometry, lbf_batch_flow or lbf_batch_time_steps. */
+lbf_status lbf_batch_resume(lbf_batch b, long more_steps, int check_every, double tol,
+                            double *eps_host, double *product_flux_host, long *steps_host);
 /* Concentration of one species of instance i (Real [ny_i][nx_i]). */
 lbf_status lbf_batch_get_concentration(lbf_batch b, int instance, int species, void *out_dev);
 lbf_status lbf_batch_time_steps(lbf_batch b, long nsteps, double *ms);

@@ -584,15 +584,26 @@ class Batch:
         self._call("lbf_batch_flow", int(max_steps), int(check_every), float(tol))
 
     def run(self, max_steps, check_every=1000, tol=0.0, raise_not_converged=False):
-        """(eps[n], product_flux[n], steps[n]) as numpy arrays."""
+        """(eps[n], product_flux[n], steps[n]) as numpy arrays.  Afterwards
+        ``all_converged`` says whether every instance passed its test."""
+        return self._advance("lbf_batch_run", max_steps, check_every, tol, raise_not_converged)
+
+    def resume(self, more_steps, check_every=1000, tol=0.0, raise_not_converged=False):
+        """Continue the current run by more_steps steps (same outputs)."""
+        return self._advance("lbf_batch_resume", more_steps, check_every, tol,
+                             raise_not_converged)
+
+    def _advance(self, name, nsteps, check_every, tol, raise_not_converged):
         eps = (ctypes.c_double * self.n)()
         prod = (ctypes.c_double * self.n)()
         steps = (ctypes.c_long * self.n)()
-        st = lib().lbf_batch_run(self._h, int(max_steps), int(check_every), float(tol), eps, prod,
-                                 steps)
+        st = getattr(lib(), name)(self._h, int(nsteps), int(check_every), float(tol), eps, prod,
+                                  steps)
         if st != _lib.OK and (st != _lib.ENOTCONV or raise_not_converged):
             msg = lib().lbf_batch_last_error(self._h).decode()
-            raise LbfError(st, f"lbf_batch_run: {msg}")
+            cls = LbfNotConverged if st == _lib.ENOTCONV else LbfError
+            raise cls(st, f"{name}: {msg}")
+        self.all_converged = st == _lib.OK and tol > 0
         return np.array(eps[:]), np.array(prod[:]), np.array(steps[:])
 
     def concentration(self, i, species):

@@ -95,6 +95,7 @@ SIGNATURES = {
     "lbf_batch_set_geometry": (_I, [_P, _P, _P]),
     "lbf_batch_flow": (_I, [_P, _L, _I, _D]),
     "lbf_batch_run": (_I, [_P, _L, _I, _D, _PD, _PD, _PL]),
+    "lbf_batch_resume": (_I, [_P, _L, _I, _D, _PD, _PD, _PL]),
     "lbf_batch_get_concentration": (_I, [_P, _I, _I, _P]),
     "lbf_batch_time_steps": (_I, [_P, _L, _PD]),
     "lbf_batch_last_error": (ctypes.c_char_p, [_P]),

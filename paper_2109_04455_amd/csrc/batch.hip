@@ -259,6 +259,15 @@ struct lbf_batch_s {
     std::map<std::tuple<int, long, int>, hipGraphExec_t> graphs;
     std::vector<int> parity_of;  // ADR lattice holding each instance's current state
     std::vector<long> steps_of;
+    // state of the current ADR run (lbf_batch_run starts it, lbf_batch_resume
+    // continues it): active instances, the eps of each one's last check, its
+    // last observables and step count, the steps taken by the run
+    bool running = false;
+    std::vector<int> act;
+    std::vector<double> prev, eps, prod;
+    std::vector<long> steps_i;
+    long steps = 0;
+    int nact = 0;
 };
 
 namespace {
@@ -641,6 +650,7 @@ lbf_status lbf_batch_set_geometry(lbf_batch b, const uint8_t *type_cat, const do
         off += (size_t)c->p.nx * c->p.ny;
     }
     b->geometry = true;
+    b->running = false;
     return LBF_OK;
 }
 
@@ -648,6 +658,7 @@ lbf_status lbf_batch_flow(lbf_batch b, long max_steps, int check_every, double t
 {
     if (!b || !b->ws || !b->geometry) return bfail(b, LBF_ESTATE, "geometry not set");
     if (check_every < 1 || max_steps < 0) return bfail(b, LBF_EINVAL, "bad step counts");
+    b->running = false;
     for (int i = 0; i < b->n; ++i) {
         Ctx *c = &b->ctx[i];
         hipError_t e = launch_flow_init(c->p.real_bytes, flow_args<float>(c, 1), flow_args<double>(c, 1),
@@ -716,12 +727,79 @@ lbf_status lbf_batch_flow(lbf_batch b, long max_steps, int check_every, double t
     return LBF_OK;
 }
 
+namespace {
+
+// Advance the current run by `more` steps (checks every check_every steps
+// counted from the start of the run), dropping instances whose check is
+// steady; then hand each instance's state and observables out.
+lbf_status batch_advance(lbf_batch b, long more, int check_every, double tol, double *eps_host,
+                         double *prod_host, long *steps_host)
+{
+    const int ns = b->p[0].nspecies;
+    const long end = b->steps + more;
+    std::vector<double> o;
+    while (b->steps < end && b->nact > 0) {
+        const long n = std::min<long>(check_every - b->steps % check_every, end - b->steps);
+        for (long left = n; left > 0;) {
+            const long m = std::min<long>(left, 1000);
+            lbf_status st = batch_steps(b, KIND_ADR, m);
+            if (st != LBF_OK) return st;
+            left -= m;
+        }
+        b->steps += n;
+        const bool last = b->steps >= end;
+        const bool check = b->steps % check_every == 0;
+        if ((tol > 0 && check) || last) {
+            lbf_status st = batch_fluxes(b, o);
+            if (st != LBF_OK) return st;
+            bool changed = false;
+            for (int i = 0; i < b->n; ++i) {
+                if (!b->act[i]) continue;
+                double tot = 0;
+                for (int s = 0; s < ns; ++s) tot += o[4 * i + s];
+                if (!std::isfinite(tot)) return bfail(b, LBF_EDIVERGED, "non-finite flux");
+                const double e_i = tot != 0 ? o[4 * i + ns - 1] / tot : NAN;
+                b->eps[i] = e_i;
+                b->prod[i] = o[4 * i + ns - 1];
+                b->steps_i[i] = b->steps;
+                b->parity_of[i] = b->gpar;
+                if (!check) continue;  // a call ending between checks only observes
+                const bool conv = tol > 0 && steady_check(&o[4 * i], ns, o[4 * i + 3], e_i,
+                                                          b->prev[i], tol);
+                b->prev[i] = e_i;
+                if (conv) {
+                    b->act[i] = 0;
+                    --b->nact;
+                    changed = true;
+                }
+            }
+            if (changed && b->nact > 0) {
+                hipError_t e = set_active(b, b->act);
+                if (e != hipSuccess) return bhip(b, e, "tile table");
+            }
+        }
+    }
+    for (int i = 0; i < b->n; ++i) {
+        b->ctx[i].gpar = b->parity_of[i];
+        b->ctx[i].adr_steps = b->steps_i[i];
+        b->steps_of[i] = b->steps_i[i];
+        if (eps_host) eps_host[i] = b->eps[i];
+        if (prod_host) prod_host[i] = b->prod[i];
+        if (steps_host) steps_host[i] = b->steps_i[i];
+    }
+    if (tol > 0 && b->nact > 0) return bfail(b, LBF_ENOTCONV, "some instances did not converge");
+    return LBF_OK;
+}
+
+}  // namespace
+
 lbf_status lbf_batch_run(lbf_batch b, long max_steps, int check_every, double tol, double *eps_host,
                          double *prod_host, long *steps_host)
 {
     if (!b || !b->ws || !b->flow_done) return bfail(b, LBF_ESTATE, "run lbf_batch_flow first");
     if (check_every < 1 || max_steps < 1) return bfail(b, LBF_EINVAL, "bad step counts");
     const int ns = b->p[0].nspecies;
+    b->running = false;
     for (int i = 0; i < b->n; ++i) {
         Ctx *c = &b->ctx[i];
         hipError_t e = launch_velocity_handoff(c->p.real_bytes, c->ptr(c->off.u), c->ptr(c->off.ua),
@@ -735,61 +813,25 @@ lbf_status lbf_batch_run(lbf_batch b, long max_steps, int check_every, double to
         c->gpar = 0;
     }
     b->gpar = 0;
-    std::vector<int> act(b->n, 1);
-    hipError_t e = set_active(b, act);
+    b->act.assign(b->n, 1);
+    hipError_t e = set_active(b, b->act);
     if (e != hipSuccess) return bhip(b, e, "tile table");
-    std::vector<double> prev(b->n, NAN), eps(b->n, NAN), prod(b->n, 0.0), o;
-    std::vector<long> steps_i(b->n, 0);
-    long steps = 0;
-    int nact = b->n;
-    while (steps < max_steps && nact > 0) {
-        const long n = std::min<long>(check_every, max_steps - steps);
-        for (long left = n; left > 0;) {
-            const long m = std::min<long>(left, 1000);
-            lbf_status st = batch_steps(b, KIND_ADR, m);
-            if (st != LBF_OK) return st;
-            left -= m;
-        }
-        steps += n;
-        const bool last = steps >= max_steps;
-        if (tol > 0 || last) {
-            lbf_status st = batch_fluxes(b, o);
-            if (st != LBF_OK) return st;
-            bool changed = false;
-            for (int i = 0; i < b->n; ++i) {
-                if (!act[i]) continue;
-                double tot = 0;
-                for (int s = 0; s < ns; ++s) tot += o[4 * i + s];
-                if (!std::isfinite(tot)) return bfail(b, LBF_EDIVERGED, "non-finite flux");
-                const double e_i = tot != 0 ? o[4 * i + ns - 1] / tot : NAN;
-                eps[i] = e_i;
-                prod[i] = o[4 * i + ns - 1];
-                steps_i[i] = steps;
-                b->parity_of[i] = b->gpar;
-                const bool conv = steady_check(&o[4 * i], ns, o[4 * i + 3], e_i, prev[i], tol);
-                prev[i] = e_i;
-                if (conv) {
-                    act[i] = 0;
-                    --nact;
-                    changed = true;
-                }
-            }
-            if (changed && nact > 0) {
-                e = set_active(b, act);
-                if (e != hipSuccess) return bhip(b, e, "tile table");
-            }
-        }
-    }
-    for (int i = 0; i < b->n; ++i) {
-        b->ctx[i].gpar = b->parity_of[i];
-        b->ctx[i].adr_steps = steps_i[i];
-        b->steps_of[i] = steps_i[i];
-        if (eps_host) eps_host[i] = eps[i];
-        if (prod_host) prod_host[i] = prod[i];
-        if (steps_host) steps_host[i] = steps_i[i];
-    }
-    if (tol > 0 && nact > 0) return bfail(b, LBF_ENOTCONV, "some instances did not converge");
-    return LBF_OK;
+    b->prev.assign(b->n, NAN);
+    b->eps.assign(b->n, NAN);
+    b->prod.assign(b->n, 0.0);
+    b->steps_i.assign(b->n, 0);
+    b->steps = 0;
+    b->nact = b->n;
+    b->running = true;
+    return batch_advance(b, max_steps, check_every, tol, eps_host, prod_host, steps_host);
+}
+
+lbf_status lbf_batch_resume(lbf_batch b, long more_steps, int check_every, double tol,
+                            double *eps_host, double *prod_host, long *steps_host)
+{
+    if (!b || !b->ws || !b->running) return bfail(b, LBF_ESTATE, "no run to resume (lbf_batch_run first)");
+    if (check_every < 1 || more_steps < 1) return bfail(b, LBF_EINVAL, "bad step counts");
+    return batch_advance(b, more_steps, check_every, tol, eps_host, prod_host, steps_host);
 }
 
 lbf_status lbf_batch_get_concentration(lbf_batch b, int i, int species, void *out)
@@ -803,6 +845,7 @@ lbf_status lbf_batch_get_concentration(lbf_batch b, int i, int species, void *ou
 lbf_status lbf_batch_time_steps(lbf_batch b, long nsteps, double *ms)
 {
     if (!b || !b->ws || !b->flow_done) return bfail(b, LBF_ESTATE, "run lbf_batch_flow first");
+    b->running = false;  // steps every instance outside a run's bookkeeping
     std::vector<int> act(b->n, 1);
     hipError_t e = set_active(b, act);
     if (e != hipSuccess) return bhip(b, e, "tile table");

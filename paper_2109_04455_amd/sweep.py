@@ -15,9 +15,11 @@ def _params(w, **kw):
 
 
 def sweep_batched(instances, flow_steps, adr_steps, check_every=1000, tol=0.0, flow_tol=0.0,
-                  tile=(256, 1), flags=0):
+                  tile=(256, 1), flags=0, chunk=None, progress=None):
     """Returns dict(eps, product_flux, steps, seconds, setup_seconds,
-    flow_seconds, adr_seconds)."""
+    flow_seconds, adr_seconds).  chunk: run the ADR in calls of that many
+    steps (a multiple of check_every; the run resumes, so the stop steps are
+    those of one call), calling progress(steps_done, active) after each."""
     import paper_2109_04455_amd as L
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -28,7 +30,17 @@ def sweep_batched(instances, flow_steps, adr_steps, check_every=1000, tol=0.0, f
     b.flow(flow_steps, check_every=check_every, tol=flow_tol)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    eps, prod, steps = b.run(adr_steps, check_every=check_every, tol=tol)
+    if chunk:
+        done = min(chunk, adr_steps)
+        eps, prod, steps = b.run(done, check_every=check_every, tol=tol)
+        while done < adr_steps and not b.all_converged:
+            if progress:
+                progress(done, int((steps == done).sum()))
+            n = min(chunk, adr_steps - done)
+            eps, prod, steps = b.resume(n, check_every=check_every, tol=tol)
+            done += n
+    else:
+        eps, prod, steps = b.run(adr_steps, check_every=check_every, tol=tol)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     b.close()

@@ -135,6 +135,42 @@ def test_batch_convergence_drops_instances_and_keeps_their_state():
         c.close()
 
 
+def test_batch_resume_equals_one_run():
+    # the convergence run of the four cascades split into resumed calls of
+    # 3000 steps (a multiple of the check interval) stops every instance at
+    # the same step with the same state as one call
+    import json
+    import os
+    import paper_2109_04455_amd as L
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "batch_conv.json")))
+    kw = dict(ref["instances"])
+    for k in ("nx_range", "pe_range", "da_range"):
+        kw[k] = tuple(kw[k])
+    ws = batch_instances(**kw)
+    out = []
+    for split in (False, True):
+        b = L.Batch([_params(w, "f64") for w in ws])
+        b.set_geometry([w.node_type for w in ws], [w.k for w in ws])
+        b.flow(ref["flow_steps"], check_every=ref["flow_steps"], tol=0)
+        if split:
+            with pytest.raises(L.LbfError):
+                b.resume(1000, check_every=1000, tol=ref["tol"])  # no run started
+            done = 4000
+            res = b.run(done, check_every=1000, tol=ref["tol"])
+            while not b.all_converged and done < ref["budget"]:
+                res = b.resume(3000, check_every=1000, tol=ref["tol"])
+                done += 3000
+        else:
+            res = b.run(ref["budget"], check_every=1000, tol=ref["tol"])
+        assert b.all_converged
+        out.append((res, [b.concentration(i, s) for i in range(len(ws)) for s in range(3)]))
+        b.close()
+    (r1, f1), (r2, f2) = out
+    assert r1[2].tolist() == r2[2].tolist() == [r["adr_steps"] for r in ref["runs"]]
+    assert (r1[0] == r2[0]).all() and (r1[1] == r2[1]).all()
+    assert all(torch.equal(a, b) for a, b in zip(f1, f2))
+
+
 def test_sweep_instances_full_size_short():
     # the 64-instance sweep at full size, a few steps: batch == single path
     import paper_2109_04455_amd as L
