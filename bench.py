@@ -337,7 +337,46 @@ def c1_and_adjoint_leg(T=20000, M=200):
     from workloads import make_workload
     w = make_workload("C1")
     out, c32, c64 = steady_pair(w, keep=True)
-    adj = {"workload": f"C1 geometry at its steady state, T={T}, checkpoints every {M}"}
+    adj = adjoint_timing(c32, w, T, M)
+    adj["workload"] = f"C1 geometry at its steady state, T={T}, checkpoints every {M}"
+    e64, g64 = c64.adjoint(T, M, keep_trace=True)
+    g32 = adj.pop("grad_keep_trace")
+    cat = torch.as_tensor(w.node_type >= 2, device=g64.device)
+    adj["fp32_vs_fp64"] = {
+        "eps_rel_err": abs(adj["eps"] / e64 - 1),
+        "grad_rel_err": float((g32 - g64).abs().max() / g64.abs().max()),
+        "grad_rel_err_l2": float((g32 - g64)[cat].norm() / g64[cat].norm())}
+    c32.close()
+    c64.close()
+    out["adjoint"] = adj
+    return out
+
+
+def adjoint_profile_leg(T=20000, M=200, flow_steps=2000, spin_up=20000):
+    """The adjoint timing of the C1 leg after a short spin-up instead of the
+    steady state (for kernel traces: no million-step solves before it)."""
+    from workloads import make_workload
+    w = make_workload("C1")
+    c = _ctx(w, "f32")
+    c.flow_init()
+    c.flow_run(flow_steps)
+    c.adr_init()
+    c.adr_run(spin_up, tol=0)
+    adj = adjoint_timing(c, w, T, M)
+    adj.pop("grad_keep_trace")
+    adj["workload"] = (f"C1 geometry after {flow_steps} flow and {spin_up} ADR steps, T={T}, "
+                       f"checkpoints every {M}")
+    c.close()
+    return adj
+
+
+def adjoint_timing(c32, w, T, M):
+    """Wall time of the adjoint over T steps from the context's current state
+    against the forward run of the same T steps, on the checkpoint-recompute
+    path and on the path that keeps the whole trace (state restored before
+    each)."""
+    import torch
+    adj = {}
     start = c32.get_state()
     # untimed first calls: workspace allocations of the torch caching allocator
     c32.adjoint(T, M, keep_trace=False)
@@ -371,17 +410,8 @@ def c1_and_adjoint_leg(T=20000, M=200):
     keep = c32.adjoint_path(T, M)
     adj["default_path"] = "keep_trace" if keep else "recompute"
     adj["ratio"] = adj["keep_trace_ratio" if keep else "recompute_ratio"]
-    e64, g64 = c64.adjoint(T, M, keep_trace=True)
-    g32 = grads["keep_trace"]
-    cat = torch.as_tensor(w.node_type >= 2, device=g64.device)
-    adj["fp32_vs_fp64"] = {
-        "eps_rel_err": abs(adj["eps"] / e64 - 1),
-        "grad_rel_err": float((g32 - g64).abs().max() / g64.abs().max()),
-        "grad_rel_err_l2": float((g32 - g64)[cat].norm() / g64[cat].norm())}
-    c32.close()
-    c64.close()
-    out["adjoint"] = adj
-    return out
+    adj["grad_keep_trace"] = grads["keep_trace"]
+    return adj
 
 
 def c2_pe_sweep_leg(pes=(1.0, 10.0, 100.0, 1000.0)):
@@ -712,6 +742,8 @@ def main():
     ap.add_argument("--pe-sweep", nargs="?", const="1,10,100,1000", default=None,
                     help="also run C2 to steady state, FP32 and FP64, at these Pe "
                          "(comma-separated; default 1,10,100,1000)")
+    ap.add_argument("--adjoint-profile", action="store_true",
+                    help="also time the C1 adjoint after a short spin-up (for kernel traces)")
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--no-noflow", action="store_true")
     ap.add_argument("--no-rwpt", action="store_true")
@@ -852,6 +884,9 @@ def main():
     if not args.no_c1:
         log("C1 steady state FP32 / FP64 and the adjoint")
         out["c1_steady_and_adjoint"] = c1_and_adjoint_leg(args.adjoint_steps)
+    if args.adjoint_profile:
+        log("C1 adjoint after a short spin-up")
+        out["adjoint_profile"] = adjoint_profile_leg(args.adjoint_steps)
     if args.pe_sweep:
         log("C2 Pe sweep to steady state")
         out["c2_pe_sweep"] = c2_pe_sweep_leg(tuple(float(v) for v in args.pe_sweep.split(",")))
