@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "adr_device.hpp"
+#include "gather_src.hpp"
 #include "ctx.hpp"
 #include "stencil.hpp"
 
@@ -28,7 +29,6 @@ namespace lbf {
 namespace {
 
 enum { DE = 1, DN = 2, DW = 3, DS = 4 };
-constexpr unsigned BIT_E = 1u, BIT_N = 2u, BIT_W = 4u, BIT_S = 8u;
 
 template <typename Real>
 __device__ __forceinline__ Real w5(int i)
@@ -63,12 +63,11 @@ __device__ __forceinline__ void adj_gather(const BlkOf &blk_of, Off PB, Off RB, 
                                            int nx, unsigned m, Real (&lam)[S][5])
 {
     constexpr Off B = sizeof(Real);
-    const Off oE = o + DE * PB, oN = o + DN * PB, oW = o + DW * PB, oS = o + DS * PB;
     const bool in = x == 0, out = x == nx - 1;
     // z_E(x) feeds g_E(x+1), or g_W(x) by bounce-back, or the outlet rule;
     // z_W(x) feeds g_W(x-1), or g_E(x) by bounce-back / the inlet rule
-    const Off src[5] = {o, (out || (m & BIT_E)) ? oW : oE + B, (m & BIT_N) ? oS : oN + RB,
-                        (in || (m & BIT_W)) ? oE : oW - B, (m & BIT_S) ? oN : oS - RB};
+    Off src[5];
+    gather::adj_sources<Off>(B, PB, RB, o, x, nx, m, src);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const auto nu = blk_of(s);

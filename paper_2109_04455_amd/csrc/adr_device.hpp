@@ -10,6 +10,7 @@
 // FP64 arithmetic costs no time.
 #pragma once
 
+#include "gather_src.hpp"
 #include "stencil.hpp"
 
 namespace lbf {
@@ -42,15 +43,12 @@ __device__ __forceinline__ void pull5_at(const Blk &blk, Off PB, Off RB, Off o, 
 {
     using R = typename Blk::real_type;
     constexpr Off B = sizeof(R);
-    const Off oE = o + DE * PB, oN = o + DN * PB, oW = o + DW * PB, oS = o + DS * PB;
+    const Off oN = o + DN * PB, oW = o + DW * PB, oS = o + DS * PB;
     const bool in = x == 0, out = x == nx - 1;
-    // E arrives from x - 1, N from y - 1, W from x + 1, S from y + 1
-    const Off sE = (in || (m & BIT_W)) ? oW : oE - B;
-    const Off sN = (m & BIT_S) ? oS : oN - RB;
-    const Off sW = (out || (m & BIT_E)) ? oE : oW + B;
-    const Off sS = (m & BIT_N) ? oN : oS + RB;
-    const R r0 = blk.load(o), rE = blk.load(sE), rN = blk.load(sN), rW = blk.load(sW),
-            rS = blk.load(sS);
+    Off src[5];
+    gather::adr_sources<Off>(B, PB, RB, o, x, nx, m, src);
+    const R r0 = blk.load(src[0]), rE = blk.load(src[DE]), rN = blk.load(src[DN]),
+            rW = blk.load(src[DW]), rS = blk.load(src[DS]);
     h[0] = Acc(r0);
     h[DE] = Acc(rE);
     h[DN] = Acc(rN);
@@ -90,10 +88,10 @@ __device__ __forceinline__ void pullS_at(const BlkOf &blk_of, Off PB, Off RB, Of
     using BlkT = decltype(blk_of(0));
     using R = typename BlkT::real_type;
     constexpr Off B = sizeof(R);
-    const Off oE = o + DE * PB, oN = o + DN * PB, oW = o + DW * PB, oS = o + DS * PB;
+    const Off oN = o + DN * PB, oW = o + DW * PB, oS = o + DS * PB;
     const bool in = x == 0, out = x == nx - 1;
-    const Off src[5] = {o, (in || (m & BIT_W)) ? oW : oE - B, (m & BIT_S) ? oS : oN - RB,
-                        (out || (m & BIT_E)) ? oE : oW + B, (m & BIT_N) ? oN : oS + RB};
+    Off src[5];
+    gather::adr_sources<Off>(B, PB, RB, o, x, nx, m, src);
     R r[S][5];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
