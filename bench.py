@@ -65,7 +65,8 @@ def flow_bytes_per_step(node_type, real_bytes):
     return fluid * (2 * 9 * real_bytes + 2) + (node_type.size - fluid) * 2
 
 
-ADR_KERNEL_SOURCES = ("kernels_adr.hip", "adr_device.hpp", "stencil.hpp", "lbf_internal.hpp")
+ADR_KERNEL_SOURCES = ("kernels_adr.hip", "adr_device.hpp", "gather_src.hpp", "stencil.hpp",
+                      "lbf_internal.hpp")
 
 
 def kernel_source_hash():
