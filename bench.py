@@ -432,16 +432,19 @@ def c2_pe_sweep_leg(pes=(1.0, 10.0, 100.0, 1000.0)):
     return out
 
 
-def batch_leg(steps=2000, flow_steps=2000, cpu=True, tts_steps=0, tts_tol=STEADY_TOL,
+def batch_leg(steps=20000, flow_steps=2000, cpu=True, tts_steps=0, tts_tol=STEADY_TOL,
               tts_flow_steps=400_000, tts_flow_tol=1e-5):
     """The 64-instance Pe x Da sweep for a fixed number of steps: one batched
     launch per step (tile shape and launch mode chosen by the autotuner) vs
     the same instances run one after another through the single-lattice path
-    (each with its own captured graphs).  With tts_steps: the sweep to
+    (each with its own captured graphs), and FP32 eps_i against the FP64
+    batched sweep over the same steps.  With tts_steps: the sweep to
     convergence (flows to tts_flow_tol, every instance until a check is
     steady or tts_steps), batched vs serial, and FP32 eps_i against the FP64
     batch at the same step counts."""
     import dataclasses
+
+    import numpy as np
     from paper_2109_04455_amd.autotune import autotune_batch
     from paper_2109_04455_amd.sweep import sweep_batched, sweep_serial
     from workloads import batch_instances
@@ -449,9 +452,21 @@ def batch_leg(steps=2000, flow_steps=2000, cpu=True, tts_steps=0, tts_tol=STEADY
     nodes = sum(w.nx * w.ny for w in ws)
     best, timings = autotune_batch(ws)
     tile, flags = (best[0], best[1]), best[2]
+    log(f"  {steps} steps of all 64 instances: batched")
     b = sweep_batched(ws, flow_steps, steps, check_every=1000, tile=tile, flags=flags)
+    log(f"  serial ({b['seconds']:.1f} s batched)")
     s = sweep_serial(ws, flow_steps, steps, check_every=1000)
     same = bool((b["product_flux"] == s["product_flux"]).all())
+    # FP32 eps_i against the FP64 batched sweep over the same steps
+    log(f"  FP64 batched ({s['seconds']:.1f} s serial)")
+    b64f = sweep_batched([dataclasses.replace(w, real="f64") for w in ws], flow_steps, steps,
+                         check_every=1000, tile=tile, flags=flags)
+    # relative error where the product has reached the outlet (eps >= 1e-6;
+    # early on a slow instance's eps is ~1e-30 and its relative error
+    # meaningless), absolute error over all instances
+    okf = np.abs(b64f["eps"]) >= 1e-6
+    relf = np.abs(b["eps"][okf] / b64f["eps"][okf] - 1)
+    absf = np.abs(b["eps"] - b64f["eps"])
     tts = None
     if tts_steps > 0:
         log(f"  sweep to convergence (at most {tts_steps} ADR steps): batched")
@@ -494,6 +509,9 @@ def batch_leg(steps=2000, flow_steps=2000, cpu=True, tts_steps=0, tts_tol=STEADY
             "batched_setup_s": round(b["setup_seconds"], 3),
             "serial_setup_s": round(s["setup_seconds"], 3),
             "identical_results": same,
+            "fp32_vs_fp64_eps_rel_err_max": float(relf.max()) if relf.size else None,
+            "fp32_vs_fp64_rel_compared": int(okf.sum()),
+            "fp32_vs_fp64_eps_abs_err_max": float(absf.max()),
             "cpu_oracle": cpu_sweep_baseline() if cpu else None,
             "time_to_solution": tts}
 
@@ -737,7 +755,7 @@ def main():
     ap.add_argument("--no-c1", action="store_true", help="skip C1 steady state and the adjoint")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=20000)
-    ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--batch-steps", type=int, default=20000)
     ap.add_argument("--batch-tts-steps", type=int, default=0,
                     help="also run the sweep to convergence, capped at this many ADR steps")
     ap.add_argument("--pe-sweep", nargs="?", const="1,10,100,1000", default=None,
