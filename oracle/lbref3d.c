@@ -30,7 +30,7 @@
  * w0 = 1/4, w1..6 = 1/8, so cs^2 = 1/4 and D = (tau_g - 1/2)/4; equilibrium
  * w_i C (1 + c.u/cs^2 + (c.u)^2/(2 cs^4) - u.u/(2 cs^2)).  Link reactions as in
  * 2D; inlet x = 0 and outlet x = nx-1 as in Eq. BC; periodic in y and z (the
- * paper's "remainder of the boundaries").
+ * paper leaves its other boundaries periodic).
  */
 #include <math.h>
 #include <stdint.h>

@@ -12,8 +12,9 @@
 // e_i = w_i (1 + p_i), p_i = 3 c.u + 4.5 (c.u)^2 - 1.5 u.u.
 //
 // Paper: Sec. "Lattice-Boltzmann for Advection-Diffusion-Reaction" (Eqs.
-// LBE_ADE, BGK, second-order equilibrium with cs^2 = 1/3, source_lbm applied
-// only to populations that stream into a reactive boundary node) and Sec.
+// LBE_ADE, BGK, second-order equilibrium with cs^2 = 1/3; the reaction
+// source of Eq. source_lbm acts on a link only when its population heads into
+// a catalytic solid node) and Sec.
 // "Boundary conditions and flux computation in ADE" (Eq. BC, inlet C_A = 1
 // with bounce-back for the other species, outlet C_w = C_b, outflux plane
 // two nodes before the right boundary).

@@ -307,7 +307,7 @@ def test_direct_steady_gradient_matches_finite_differences(tiny_flow):
         assert abs(grad[y, x] - fd) < 1e-7 * abs(fd)
 
 
-# ------------------------- the paper's "all populations react" comparison variant
+# ------------- the paper's comparison variant: every population of the node reacts
 def _closed_box_disc(kind=CAT1, k=0.3):
     nx, ny = 40, 30
     t = np.zeros((ny, nx), np.uint8)
