@@ -30,6 +30,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import subprocess
 import sys
 import time
@@ -69,11 +70,21 @@ ADR_KERNEL_SOURCES = ("kernels_adr.hip", "adr_device.hpp", "gather_src.hpp", "st
                       "lbf_internal.hpp")
 
 
-def kernel_source_hash():
-    """Hash of every source the ADR step kernels are compiled from."""
+def code_of(text):
+    """C++ source without comments and blank lines."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = (re.sub(r"//.*", "", line).rstrip() for line in text.splitlines())
+    return "\n".join(line for line in lines if line)
+
+
+def kernel_source_hash(read=None):
+    """Hash of the code (comments and blank lines removed) of every source the
+    ADR step kernels are compiled from."""
+    read = read or (lambda name: open(os.path.join(ROOT, "paper_2109_04455_amd", "csrc",
+                                                   name)).read())
     h = hashlib.sha256()
     for name in ADR_KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, "paper_2109_04455_amd", "csrc", name), "rb").read())
+        h.update(code_of(read(name)).encode())
     return h.hexdigest()[:16]
 
 
