@@ -147,14 +147,17 @@ lbf_status lbf_set_geometry(lbf_ctx ctx, const uint8_t *node_type_dev);
  * at node types 2 and 3).  Values must lie in [0, 1] (LBF_EINVAL).  Syncs. */
 lbf_status lbf_set_rates(lbf_ctx ctx, const double *k_dev);
 
-/* Flow: initial state f = f_eq(rho = 1, u = (u_in(y), 0)) with the parabola
+/* Flow (Sec. "Lattice-Boltzmann for the Navier-Stokes equation", Eq. LBE,
+ * with a velocity inlet and a pressure outlet in place of the paper's body
+ * force): initial state f = f_eq(rho = 1, u = (u_in(y), 0)) with the parabola
  * u_in(y) = 4 u0 (y - 1/2)(ny - 3/2 - y)/(ny - 2)^2.  Channel only
  * (LBF_EINVAL for a periodic box). */
 lbf_status lbf_flow_init(lbf_ctx ctx);
-/* Advance the flow by exactly nsteps steps (asynchronous). */
+/* Advance the flow by exactly nsteps D2Q9 BGK steps (Eq. LBE; asynchronous). */
 lbf_status lbf_flow_run(lbf_ctx ctx, long nsteps);
 /* Advance until max |u(t) - u(t - check_every)| <= tol * u0 over fluid nodes,
- * or max_steps (then LBF_ENOTCONV).  tol <= 0: run exactly max_steps.
+ * or max_steps (then LBF_ENOTCONV): the steady Stokes flow the paper solves
+ * once per geometry and scales.  tol <= 0: run exactly max_steps.
  * Synchronises; *steps_done and *residual (max |du|) may be NULL. */
 lbf_status lbf_flow_steady(lbf_ctx ctx, long max_steps, int check_every, double tol,
                            long *steps_done, double *residual);
@@ -163,14 +166,20 @@ lbf_status lbf_get_velocity(lbf_ctx ctx, void *ux_dev, void *uy_dev);
 /* Import a flow velocity, Real [ny][nx] (replaces the flow solve). */
 lbf_status lbf_set_velocity(lbf_ctx ctx, const void *ux_dev, const void *uy_dev);
 
-/* ADR: species A at equilibrium with C = c_in and u = vel_scale * u_flow at
- * every fluid node, B and C zero.  Resets the step counter. */
+/* ADR (Sec. "Lattice-Boltzmann for Advection-Diffusion-Reaction"): species A
+ * at equilibrium with C = c_in and u = vel_scale * u_flow at every fluid
+ * node, B and C zero.  Resets the step counter. */
 lbf_status lbf_adr_init(lbf_ctx ctx);
-/* Advance up to max_steps; every check_every steps compute eps and stop when
- * |eps - eps_prev| <= tol |eps| (LBF_ENOTCONV when max_steps is reached
- * first).  tol <= 0: run exactly max_steps (asynchronous unless checks are
- * requested).  check_every must be >= 1.  *steps_done may be NULL.  A
- * periodic box has no eps: it takes tol <= 0 only (LBF_EINVAL otherwise). */
+/* Advance up to max_steps of the ADR step (Eqs. LBE_ADE, BGK, source_lbm,
+ * boundary rules of Eq. BC).  Every check_every steps of the call compute the
+ * outlet fluxes and eps (Eq. A-B) and stop at a steady check: eps moved by at
+ * most tol of itself since the call's previous check, the outflux of the
+ * last species is positive and N_A + ... + N_last balances the inflow of A
+ * within 1e-3 of it (LBF_ENOTCONV when max_steps is reached first; a call's
+ * first check has no previous eps).  tol <= 0: run exactly max_steps
+ * (asynchronous unless checks are requested).  check_every must be >= 1.
+ * *steps_done may be NULL.  A periodic box has no eps: it takes tol <= 0 only
+ * (LBF_EINVAL otherwise). */
 lbf_status lbf_adr_run(lbf_ctx ctx, long max_steps, int check_every, double tol,
                        long *steps_done);
 /* Outlet fluxes N[0..nspecies) of the last step (FP64 sums over the rows
@@ -202,7 +211,9 @@ lbf_status lbf_adr_production(lbf_ctx ctx, double *rates);
 /* Number of ADR steps taken since lbf_adr_init. */
 lbf_status lbf_adr_steps(lbf_ctx ctx, long *steps);
 
-/* Adjoint (reverse-mode) gradient of eps with respect to the rate k(x).
+/* Adjoint (reverse-mode) gradient of eps with respect to the rate k(x): the
+ * exact derivative of the forward scheme (Eq. source_lbm supplies the only
+ * dependence on k), not a method of the paper.
  * Objective: eps after T further steps from the current state, the current
  * pre-collision populations held fixed: the window's first collision and
  * reaction use the rates set at the call (the current post-collision lattice
