@@ -90,8 +90,10 @@ lbf_status lbf3_set_velocity(lbf3_ctx ctx, const void *ux_dev, const void *uy_de
 
 /* ADR: A at equilibrium with C = c_in and u = vel_scale * u_flow, B = C = 0. */
 lbf_status lbf3_adr_init(lbf3_ctx ctx);
-/* As lbf_adr_run: up to max_steps, stopping when |eps - eps_prev| <= tol |eps|
- * at a check (tol <= 0: exactly max_steps). */
+/* As lbf_adr_run: up to max_steps, stopping at a steady check (eps moved by
+ * at most tol of itself since the call's previous check, positive outflux of
+ * the last species, outlet fluxes balancing the inflow of A within 1e-3;
+ * tol <= 0: exactly max_steps). */
 lbf_status lbf3_adr_run(lbf3_ctx ctx, long max_steps, int check_every, double tol,
                         long *steps_done);
 /* Outlet fluxes N[0..nspecies), inflow of A and eps of the last step (FP64
