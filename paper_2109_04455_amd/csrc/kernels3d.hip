@@ -326,6 +326,51 @@ __device__ __forceinline__ void pull7(const Blk &lat, int q0, const Off (&so)[7]
     }
 }
 
+// The same for all S species of the node at once (species s at populations
+// 7s .. 7s+6): the sources are chosen by offset and all 7 S loads are issued
+// before any is converted to Acc.  A branch per direction with the
+// conversion inside made each species wait for its loads in turn.  Outlet
+// nodes read their own populations for the outlet rule afterwards.  Same
+// results as pull7 per species.
+template <typename Real, typename Acc, int S, typename Blk, typename Off>
+__device__ __forceinline__ void pull7S(const Blk &lat, const Off (&so)[7], int x, int nx,
+                                       unsigned m, Acc inlet_e, Acc (&h)[S][7])
+{
+    constexpr Off QB = SEG * sizeof(Real);
+    const bool in = x == 0, out = x == nx - 1;
+    Off src[7];
+    src[0] = so[0];
+    src[1] = (in || (m & 2u)) ? so[0] + 2 * QB : so[2] + 1 * QB;   // +x from x - 1
+    src[2] = (out || (m & 1u)) ? so[0] + 1 * QB : so[1] + 2 * QB;  // -x from x + 1
+#pragma unroll
+    for (int d = 3; d < 7; ++d) {
+        const int o = d & 1 ? d + 1 : d - 1;
+        src[d] = ((m >> (o - 1)) & 1u) ? so[0] + (Off)o * QB : so[o] + (Off)d * QB;
+    }
+    Real r[S][7];
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int d = 0; d < 7; ++d) r[s][d] = lat.load(src[d] + (Off)(7 * s) * QB);
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int d = 0; d < 7; ++d) h[s][d] = Acc(r[s][d]);
+    if (in) h[0][1] = inlet_e - h[0][1];
+    if (out) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            // h[s][2] holds the node's own +x population here
+            Acc sum = Acc(0);
+            sum += h[s][0];
+            sum += h[s][2];
+#pragma unroll
+            for (int j = 2; j < 7; ++j) sum += Acc(lat.load(so[0] + (Off)(7 * s + j) * QB));
+            h[s][2] = Acc(2) * w7<Acc>(2) * sum - h[s][2];
+        }
+    }
+}
+
 // Indices of the six neighbours x + c_d (x unwrapped: only used in range).
 template <typename Idx>
 __device__ __forceinline__ void neighbours7(const Geo &g, int x, int y, int z, Idx (&nb)[7])
@@ -422,8 +467,7 @@ __global__ __launch_bounds__(1024) void k_adr_step3(AdrArgs3<Real> a)
     const PopBlock<Real, false, true> vel(a.ua, 3 * PB);
     const Acc inlet_e = Acc(2) * w7<Acc>(1) * (Acc(a.cin) - Acc(a.cref));
     Acc h[S][7];
-#pragma unroll
-    for (int s = 0; s < S; ++s) pull7<Real, Acc, NQ>(in, 7 * s, so, x, g.nx, m, s == 0, inlet_e, h[s]);
+    pull7S<Real, Acc, S>(in, so, x, g.nx, m, inlet_e, h);
     const Off ob = id * (Off)sizeof(Real);
     collide_react7<Real, Acc, S>(a, m, nb, Acc(vel.load(ob)), Acc(vel.load(ob + PB)),
                                  Acc(vel.load(ob + 2 * PB)), h);
