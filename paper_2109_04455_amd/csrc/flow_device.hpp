@@ -140,16 +140,15 @@ __device__ __forceinline__ void node_update(const FlowArgs<Real> &a, int x, int 
     constexpr Off B = sizeof(Real);
     const Off PB = (Off)a.plane * B, o = (Off)id * B;
     const PopBlock<Real, NT, WIDE> in(a.src, 9 * PB);
+    // all nine loads before any use (an open source reads the node's own
+    // slot, which Zou-He then replaces): no wait per direction
+    Real r[9];
+    bool open[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) r[i] = in.load(source_off<Off>(i, x, a.nx, a.nxp, m, o, PB, B, open[i]));
     Acc h[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        bool open;
-        const Off off = source_off<Off>(i, x, a.nx, a.nxp, m, o, PB, B, open);
-        if (open)
-            h[i] = 0;
-        else
-            h[i] = Acc(in.load(off));
-    }
+    for (int i = 0; i < 9; ++i) h[i] = open[i] ? Acc(0) : Acc(r[i]);
     finish_node<Real, Acc, WRITE_U, NT, WIDE>(a, x, y, id, h);
 }
 
