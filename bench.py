@@ -507,9 +507,10 @@ def batch_leg(steps=20000, flow_steps=2000, cpu=True, tts_steps=0, tts_tol=STEAD
                "fp32_vs_fp64_eps_rel_err_max": float(rel.max()) if rel.size else None,
                "fp32_vs_fp64_compared": int(ok.sum())}
     return {"instances": len(ws), "nodes": nodes, "steps": steps,
-            "autotuned": {"tile": list(tile), "mode": ("one block per tile" if flags & 8 else
-                                                    "persistent tile walk") +
-                          ("" if flags & 256 else ", two ADR steps per launch"),
+            "autotuned": {"tile": list(tile),
+                          "mode": ("one ADR step per launch, " +
+                                   ("one block per tile" if flags & 8 else "persistent tile walk"))
+                          if flags & 256 else "two ADR steps per launch, one block per tile",
                           "us_per_step": {str(k): round(v, 2) for k, v in timings.items()}},
             "batched_adr_s": round(b["adr_seconds"], 4), "serial_adr_s": round(s["adr_seconds"], 4),
             "batched_mlups": round(nodes * steps / b["adr_seconds"] / 1e6, 1),

@@ -87,7 +87,9 @@ typedef struct {
                             together with bit 4, LBF_EINVAL: the A field error
                             then reaches ~2e-4 of its maximum on a 512 x 128
                             cascade, against ~1e-6 shifted); bit 3 (batch):
-                            one block per tile instead of the persistent tile walk;
+                            one-step ADR launches take one block per tile instead
+                            of the persistent tile walk (the batched flow always
+                            takes one block per tile);
                             bit 4: FP32 arithmetic for FP32 storage (default: each
                             node update computes in FP64, rounding once per store);
                             bit 5: FP32 arithmetic in the flow step only.

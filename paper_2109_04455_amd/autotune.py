@@ -83,8 +83,9 @@ BATCH_CANDIDATES = (
     # (tile_x, tile_y, flags): flags bit 8 = one ADR step per launch instead
     # of two; bit 3 = one block per tile instead of the persistent tile walk.
     # Two steps per launch use the LDS tile fixed at compile time, which tile
-    # shape and bit 3 do not change (they reach only the flow and the single
-    # steps): one candidate.  One step per launch: tile shapes, walk or not.
+    # shape and bit 3 do not change (the tile shape reaches only the flow and
+    # the single steps, bit 3 only the single steps): one candidate.  One step
+    # per launch: tile shapes, walk or not.
     (256, 1, 0),
     (256, 1, 256), (256, 1, 256 | 8), (128, 2, 256), (128, 2, 256 | 8), (64, 4, 256),
     (64, 4, 256 | 8), (128, 1, 256 | 8), (64, 1, 256 | 8),

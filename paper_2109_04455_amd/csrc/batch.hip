@@ -3,9 +3,11 @@
 //
 // Every instance keeps the single-lattice storage layout inside one
 // workspace.  A tile table lists the (instance, tile) pairs still active; one
-// persistent launch per time step walks the table (each block takes a
-// contiguous chunk of tiles, chunks handed out XCD by XCD), and blocks of
-// steps are captured once and replayed as a HIP graph.  The tile count lives
+// launch per time step (two ADR steps per launch by default) covers the
+// table, one block per slot or, for one-step ADR launches, a persistent grid
+// walking it (each block takes a contiguous chunk of tiles, chunks handed
+// out XCD by XCD), and blocks of steps are captured once and replayed as a
+// HIP graph.  The tile count lives
 // in device memory, so converged instances are dropped from the table by a
 // small compaction kernel without touching the captured graph.
 #include <algorithm>
@@ -54,18 +56,31 @@ __device__ __forceinline__ void swap_parity(AdrArgs<Real> &a, int parity)
     }
 }
 
+// A tile table entry (instance, tile x, tile y) is the same for the whole
+// block: taking it into scalar registers lets the compiler read the
+// instance's argument block with scalar loads, instead of holding it per lane
+// in vector registers.
+__device__ __forceinline__ int4 uniform_tile(const int4 *tiles, int t)
+{
+    int4 v = tiles[t];
+    v.x = __builtin_amdgcn_readfirstlane(v.x);
+    v.y = __builtin_amdgcn_readfirstlane(v.y);
+    v.z = __builtin_amdgcn_readfirstlane(v.z);
+    return v;
+}
+
 // PERSIST: a fixed grid walks contiguous chunks of the tile table (next tile
 // prefetched, the instance's argument block reused while the instance does
 // not change).  Otherwise one block per table slot; slots past the live
 // count exit at once.
 template <typename Real, int S, bool NT, bool PERSIST, bool WIDE>
-__global__ __launch_bounds__(256) void k_batch_adr(const Inst<Real> *insts, const int4 *tiles,
+__global__ __launch_bounds__(256) void k_batch_adr(const Inst<Real> *__restrict__ insts, const int4 *__restrict__ tiles,
                                                    const int *ntiles, int parity, int tx, int ty)
 {
     const int lx = (int)threadIdx.x % tx, ly = (int)threadIdx.x / tx;
     if (!PERSIST) {
         if ((int)blockIdx.x >= *ntiles) return;
-        const int4 T = tiles[blockIdx.x];
+        const int4 T = uniform_tile(tiles, blockIdx.x);
         AdrArgs<Real> a = insts[T.x].adr;
         swap_parity(a, parity);
         const int x = T.y * tx + lx, y = T.z * ty + ly;
@@ -75,12 +90,12 @@ __global__ __launch_bounds__(256) void k_batch_adr(const Inst<Real> *insts, cons
     int t0, t1;
     chunk_of_block(*ntiles, t0, t1);
     if (t0 >= t1) return;
-    int4 T = tiles[t0];
+    int4 T = uniform_tile(tiles, t0);
     int cur = T.x;
     AdrArgs<Real> a = insts[cur].adr;
     swap_parity(a, parity);
     for (int t = t0; t < t1; ++t) {
-        const int4 Tn = t + 1 < t1 ? tiles[t + 1] : T;
+        const int4 Tn = t + 1 < t1 ? uniform_tile(tiles, t + 1) : T;
         if (T.x != cur) {
             cur = T.x;
             a = insts[cur].adr;
@@ -92,36 +107,30 @@ __global__ __launch_bounds__(256) void k_batch_adr(const Inst<Real> *insts, cons
     }
 }
 
-template <typename Real, bool WRITE_U, bool NT, bool WIDE, bool PERSIST>
-__global__ __launch_bounds__(256) void k_batch_flow(const Inst<Real> *insts, const int4 *tiles,
-                                                    const int *ntiles, int parity, int tx, int ty)
+// One block per slot of the flow tile table (slots past the live count exit
+// at once): a flow tile is tx x 2 ty nodes, thread row j takes lattice rows
+// 2j and 2j + 1 of the tile (FP64 arithmetic, as the single-lattice flow).
+// The flow never walks the table with a persistent grid: for its short
+// per-tile work a walk ran about a fifth slower than one block per tile.
+template <typename Real, bool WRITE_U, bool NT, bool WIDE>
+__global__ __launch_bounds__(256) void k_batch_flow(const Inst<Real> *__restrict__ insts,
+                                                    const int4 *__restrict__ tiles,
+                                                    const int *__restrict__ ntiles, int parity,
+                                                    int tx, int ty)
 {
-    // a flow tile is tx x 2 ty nodes: thread row j takes lattice rows 2j and
-    // 2j + 1 of the tile (FP64 arithmetic, as the single-lattice flow)
-    int t0, t1;
-    if (PERSIST) {
-        chunk_of_block(*ntiles, t0, t1);
-    } else {
-        // one block per table slot; slots past the live count exit at once
-        t0 = (int)blockIdx.x;
-        t1 = t0 < *ntiles ? t0 + 1 : t0;
+    if ((int)blockIdx.x >= *ntiles) return;
+    const int4 T = uniform_tile(tiles, blockIdx.x);
+    FlowArgs<Real> a = insts[T.x].flow;
+    if (parity) {
+        const Real *tmp = a.src;
+        a.src = a.dst;
+        a.dst = const_cast<Real *>(tmp);
     }
-    for (int t = t0; t < t1; ++t) {
-        const int4 T = tiles[t];
-        FlowArgs<Real> a = insts[T.x].flow;
-        if (parity) {
-            const Real *tmp = a.src;
-            a.src = a.dst;
-            a.dst = const_cast<Real *>(tmp);
-        }
-        const int x = T.y * tx + (int)threadIdx.x % tx;
-        const int y = T.z * 2 * ty + 2 * ((int)threadIdx.x / tx);
-        if (x < a.nx && y < a.ny) flow::node_update2<Real, double, WRITE_U, NT, WIDE>(a, x, y);
-    }
+    const int x = T.y * tx + (int)threadIdx.x % tx;
+    const int y = T.z * 2 * ty + 2 * ((int)threadIdx.x / tx);
+    if (x < a.nx && y < a.ny) flow::node_update2<Real, double, WRITE_U, NT, WIDE>(a, x, y);
 }
 
-// Rebuild a tile table from the per-instance active flags (one block): kind
-// 0 the one-step tiles, 1 the tiles of the two-step kernel, 2 the flow tiles.
 template <typename Real>
 __global__ void k_build_tiles(const Inst<Real> *insts, const int *active, int n, int kind,
                               int4 *tiles, int *ntiles)
@@ -161,7 +170,7 @@ __attribute__((amdgpu_waves_per_eu(adr::PairTile<Real>::OCC)))
 void k_batch_adr2(const Inst<Real> *insts, const int4 *tiles, const int *ntiles, int parity)
 {
     if ((int)blockIdx.x >= *ntiles) return;
-    const int4 T = tiles[blockIdx.x];
+    const int4 T = uniform_tile(tiles, blockIdx.x);
     AdrArgs<Real> a = insts[T.x].adr;
     swap_parity(a, parity);
     adr::pair_update<Real, double, S, NT, WIDE, false>(a, T.y, T.z);
@@ -372,18 +381,11 @@ void batch_launch(lbf_batch b, int kind, int parity, bool write_u, hipStream_t s
                 hipLaunchKernelGGL((k_batch_adr<Real, 3, NT, false, WIDE>), ga, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
         }
     } else {
-        const dim3 gf(b->persistent ? b->grid : b->max_tiles);
-        if (b->persistent) {
-            if (write_u)
-                hipLaunchKernelGGL((k_batch_flow<Real, true, NT, WIDE, true>), gf, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
-            else
-                hipLaunchKernelGGL((k_batch_flow<Real, false, NT, WIDE, true>), gf, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
-        } else {
-            if (write_u)
-                hipLaunchKernelGGL((k_batch_flow<Real, true, NT, WIDE, false>), gf, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
-            else
-                hipLaunchKernelGGL((k_batch_flow<Real, false, NT, WIDE, false>), gf, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
-        }
+        const dim3 gf(b->max_tiles);
+        if (write_u)
+            hipLaunchKernelGGL((k_batch_flow<Real, true, NT, WIDE>), gf, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
+        else
+            hipLaunchKernelGGL((k_batch_flow<Real, false, NT, WIDE>), gf, blk, 0, s, I, tiles, nt, parity, b->tx, b->ty);
     }
 }
 
