@@ -98,18 +98,20 @@ __device__ __forceinline__ void adj_local(const AdjArgs<Real> &a, const Real *tr
                                           unsigned m, Real u_, Real v_, bool own,
                                           const Real (&lam_)[S][5], Real (&out)[S][5])
 {
-    double lam[S][5], rsrc[S];
+    // lam is widened to FP64 at each use (exact), not held widened: 15
+    // storage-width registers instead of 30 while the link loads travel
+    const auto lam = [&](int s, int i) { return (double)lam_[s][i]; };
+    double rsrc[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-        rsrc[s] = 0;
-#pragma unroll
-        for (int i = 0; i < 5; ++i) lam[s][i] = (double)lam_[s][i];
-    }
+    for (int s = 0; s < S; ++s) rsrc[s] = 0;
     if (m & 0xF0u) {
         const int off[5] = {0, 1, a.nxp, -1, -a.nxp};
         const int t = a.trace_idx[id];
-        // rate and type of the four neighbours loaded together (index
-        // clamped into the plane), used where a link bit is set
+        // everything the links need is loaded before any use: rate and type
+        // of the four neighbours (index clamped into the plane), the trace,
+        // and for the owning block the node's four link accumulators (a
+        // load issued only after a link's term is known would put its
+        // latency on every catalytic-adjacent node's path)
         Real kv[5];
         uint8_t tv[5];
 #pragma unroll
@@ -120,21 +122,33 @@ __device__ __forceinline__ void adj_local(const AdjArgs<Real> &a, const Real *tr
             tv[i] = a.type[sid];
         }
         const double ca = (double)trace[2 * t], cb = (double)trace[2 * t + 1];
+        double *acc = a.acc + 4 * (size_t)t;
+        double ac[4] = {0, 0, 0, 0};
+        if (own) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ac[i] = acc[i];
+        }
 #pragma unroll
         for (int i = 1; i < 5; ++i) {
             if (!((m >> (3 + i)) & 1u)) continue;
             const double kap = (double)kv[i] * w5<double>(i);
             double g;
             if (tv[i] == 2) {
-                const double d = lam[1][i] - lam[0][i];
+                const double d = lam(1, i) - lam(0, i);
                 g = w5<double>(i) * ca * d;
                 rsrc[0] += kap * d;
             } else {
-                const double d = lam[S - 1][i] - lam[1][i];
+                const double d = lam(S - 1, i) - lam(1, i);
                 g = w5<double>(i) * cb * d;
                 rsrc[1] += kap * d;
             }
-            if (own) a.acc[4 * t + i - 1] += g;
+            ac[i - 1] += g;
+        }
+        // the node's accumulators have one owner: links without a reaction
+        // write back their unchanged value
+        if (own) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[i] = ac[i];
         }
     }
     // (R Col)^T: nu_j = (1 - omega) lam_j + omega sum_i e_i lam_i + rsrc
@@ -148,11 +162,11 @@ __device__ __forceinline__ void adj_local(const AdjArgs<Real> &a, const Real *tr
     const double keep = 1.0 - a.omega;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        const double M = e[0] * lam[s][0] + e[1] * lam[s][1] + e[2] * lam[s][2] +
-                         e[3] * lam[s][3] + e[4] * lam[s][4];
+        const double M = e[0] * lam(s, 0) + e[1] * lam(s, 1) + e[2] * lam(s, 2) +
+                         e[3] * lam(s, 3) + e[4] * lam(s, 4);
         const double add = a.omega * M + rsrc[s];
 #pragma unroll
-        for (int i = 0; i < 5; ++i) out[s][i] = Real(keep * lam[s][i] + add);
+        for (int i = 0; i < 5; ++i) out[s][i] = Real(keep * lam(s, i) + add);
     }
 }
 
