@@ -85,6 +85,34 @@ def test_two_step_adjoint_equals_single_steps(tiny_ref, real, tol, keep, ckpt):
     assert abs(e2 / e1 - 1) <= tol
 
 
+@pytest.mark.parametrize("real,tol", [("f64", 1e-11), ("f32", 1e-4)])
+def test_recompute_path_equals_keep_trace(tiny_ref, real, tol):
+    # the recompute path replays each checkpoint segment's trace before the
+    # segment's adjoint steps.  Over segment lengths 1 (nothing to replay),
+    # 2, 7 and 64 (ragged last segments of T = 1000) its gradient and eps
+    # equal the keep-trace path's to round-off: the paths group steps into
+    # two-step launches differently, nothing else
+    w, flow_steps, n0, T, _, _ = tiny_ref
+    c = _ctx(w, real)
+    c.flow_init()
+    c.flow_run(flow_steps)
+    c.adr_init()
+    c.adr_run(n0, tol=0)
+    start = c.get_state()
+    eps_k, grad_k = c.adjoint(T, ckpt_every=200, keep_trace=True)
+    grad_k = grad_k.cpu().numpy()
+    scale = np.abs(grad_k).max()
+    assert scale > 0
+    for M in (1, 2, 7, 64):
+        c.set_state(start)
+        eps_r, grad_r = c.adjoint(T, ckpt_every=M, keep_trace=False)
+        d = np.abs(grad_r.cpu().numpy() - grad_k).max() / scale
+        print(real, "segment", M, "max |recompute - keep| / max |grad|", d, flush=True)
+        assert d <= tol
+        assert abs(eps_r / eps_k - 1) <= 1e-12
+    c.close()
+
+
 def test_adjoint_long_window_tends_to_steady_adjoint():
     w = make_workload("tiny")
     ux, uy, _, _ = R.flow_steady(w.node_type, w.tau_f, w.u0, 3000, tol=0)
