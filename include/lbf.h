@@ -109,7 +109,10 @@ typedef struct {
                             link-reaction channel run two per launch, the
                             intermediate state kept in LDS; the last step of
                             every block is a single one); the adjoint's steps
-                            likewise;
+                            likewise, and the flow's (default: two per launch
+                            on lattices of at least 2^18 nodes with FP64
+                            arithmetic, an odd block ending in a single step;
+                            results equal to one step per launch bit for bit);
                             bit 9: untraced two-step launches by wavefronts that
                             march along y with the intermediate rows in
                             registers instead of the LDS tile (FP32 storage with

@@ -149,6 +149,30 @@ hipError_t enqueue_flow_step(Ctx *c, int src_buf, bool write_u, hipStream_t s)
                             flow_args<double>(c, src_buf), s);
 }
 
+// Two-step launches in a flow block of n steps (each swaps the lattices once).
+long flow_pairs(const Ctx *c, long n) { return c->flow_pair ? n / 2 : 0; }
+
+// A flow block of n steps from lattice par: two steps per launch where the
+// context runs them, a single step for an odd remainder; the velocity is
+// written by the block's last step (its second step for a final pair).
+hipError_t enqueue_flow_block(Ctx *c, int &par, long n, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    long i = 0;
+    if (c->flow_pair) {
+        for (; i + 2 <= n && e == hipSuccess; i += 2, par ^= 1) {
+            FlowArgs<float> af = flow_args<float>(c, par);
+            FlowArgs<double> ad = flow_args<double>(c, par);
+            const bool fp32 = af.L.fp32_math;
+            af.L = ad.L = c->Lfp;
+            af.L.fp32_math = ad.L.fp32_math = fp32;
+            e = launch_flow_pair(c->p.real_bytes, i + 2 == n, af, ad, s);
+        }
+    }
+    for (; i < n && e == hipSuccess; ++i, par ^= 1) e = enqueue_flow_step(c, par, i == n - 1, s);
+    return e;
+}
+
 // The instantiated graph of n consecutive steps starting from lattice par
 // (captured and instantiated on first use).
 lbf_status graph_of(Ctx *c, int kind, long n, int par, hipGraphExec_t *out)
@@ -163,8 +187,7 @@ lbf_status graph_of(Ctx *c, int kind, long n, int par, hipGraphExec_t *out)
         if (kind == KIND_ADR) {
             le = enqueue_adr_block(c, p, n, c->cap_stream);
         } else {
-            for (long i = 0; i < n && le == hipSuccess; ++i, p ^= 1)
-                le = enqueue_flow_step(c, p, i == n - 1, c->cap_stream);
+            le = enqueue_flow_block(c, p, n, c->cap_stream);
         }
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(c->cap_stream, &g);
@@ -194,11 +217,8 @@ lbf_status run_steps(Ctx *c, int kind, long n)
             if (e != hipSuccess) return hip_fail(c, e, "step launch");
             return LBF_OK;
         }
-        for (long i = 0; i < n; ++i) {
-            hipError_t e = enqueue_flow_step(c, par, i == n - 1, c->stream);
-            if (e != hipSuccess) return hip_fail(c, e, "step launch");
-            par ^= 1;
-        }
+        hipError_t e = enqueue_flow_block(c, par, n, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "step launch");
         return LBF_OK;
     }
     hipGraphExec_t ex = nullptr;
@@ -206,7 +226,7 @@ lbf_status run_steps(Ctx *c, int kind, long n)
     if (st != LBF_OK) return st;
     hipError_t e = hipGraphLaunch(ex, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
-    const long swaps = kind == KIND_ADR ? n - adr_pairs(c, n) : n;
+    const long swaps = n - (kind == KIND_ADR ? adr_pairs(c, n) : flow_pairs(c, n));
     if (swaps & 1) par ^= 1;
     return LBF_OK;
 }
@@ -361,6 +381,21 @@ lbf_status lbf_create(const lbf_params *p, lbf_ctx *out)
         if (c->march) c->Lm = march_launch(c->Lp, p->nx, p->ny, 22);
     }
     c->flow_fp32_math = (p->flags & (16 | 32)) != 0;
+    // flow steps run two per launch (FP64 arithmetic, a channel of at least
+    // FLOW_PAIR_MIN_NODES nodes) unless flags bit 8 asks for one per launch
+    c->flow_pair = !(p->flags & 256) && p->boundary == 0 && !c->flow_fp32_math &&
+                   (long)p->nx * p->ny >= FLOW_PAIR_MIN_NODES;
+    if (c->flow_pair) {
+        int tx, ty;
+        pair_tile(p->real_bytes, tx, ty);
+        c->Lfp = c->L;
+        const Launch t = make_launch(p->nx, p->ny, tx, ty);
+        c->Lfp.tx = t.tx;
+        c->Lfp.ty = t.ty;
+        c->Lfp.gx = t.gx;
+        c->Lfp.gy = t.gy;
+        c->Lfp.vec = false;
+    }
     c->valid = true;
     return LBF_OK;
 }

@@ -23,6 +23,8 @@ struct lbf_ctx_s {
     lbf::Launch Lm;  // marching two-step launch (when `march`)
     bool pair = false;  // untraced ADR steps run two per launch
     bool march = false;  // ... by the marching kernel instead of the LDS tile
+    lbf::Launch Lfp;  // two-step flow launch (when `flow_pair`)
+    bool flow_pair = false;  // flow steps run two per launch
     bool flow_fp32_math = false;  // flow step computes in FP32 (FP32 storage)
 
     // workspace (caller-owned) and its layout
@@ -84,6 +86,13 @@ double efficiency_of(const double *N, int ns);
 hipError_t enqueue_adr_step(Ctx *c, int src_buf, hipStream_t s, void *trace_slot);
 hipError_t enqueue_adr_pair(Ctx *c, int src_buf, hipStream_t s);
 void adjoint_release(Ctx *c);
+
+// Two flow steps per launch (kernels_flow.hip): a.L is the two-step tiling.
+hipError_t launch_flow_pair(int real_bytes, bool write_u, const FlowArgs<float> &af,
+                            const FlowArgs<double> &ad, hipStream_t s);
+// Flow steps run two per launch on lattices of at least this many nodes
+// (below it a launch covers a few blocks and one row per thread is kept).
+constexpr long FLOW_PAIR_MIN_NODES = 1L << 18;
 
 // Kernel argument blocks for the context's own lattices.
 template <typename Real>

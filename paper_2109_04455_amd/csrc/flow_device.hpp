@@ -129,6 +129,27 @@ __device__ __forceinline__ void finish_node(const FlowArgs<Real> &a, int x, int 
     for (int i = 0; i < 9; ++i) out.store(o + i * PB, Real(h[i]));
 }
 
+// Gather of fluid node (x, id) with mask m from the lattice in HBM: the
+// streamed populations (bounce-back at solid sources), 0 where a population
+// enters through an open column (Zou-He fills it).  All nine loads are
+// issued before any use (an open source reads the node's own slot): no wait
+// per direction.
+template <typename Real, typename Acc, bool NT, bool WIDE>
+__device__ __forceinline__ void gather_node(const FlowArgs<Real> &a, int x, size_t id, unsigned m,
+                                            Acc (&h)[9])
+{
+    using Off = off_t_<WIDE>;
+    constexpr Off B = sizeof(Real);
+    const Off PB = (Off)a.plane * B, o = (Off)id * B;
+    const PopBlock<Real, NT, WIDE> in(a.src, 9 * PB);
+    Real r[9];
+    bool open[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) r[i] = in.load(source_off<Off>(i, x, a.nx, a.nxp, m, o, PB, B, open[i]));
+#pragma unroll
+    for (int i = 0; i < 9; ++i) h[i] = open[i] ? Acc(0) : Acc(r[i]);
+}
+
 // Full update of node (x, y): gather (bounce-back, Zou-He), collide, store.
 template <typename Real, typename Acc, bool WRITE_U, bool NT, bool WIDE>
 __device__ __forceinline__ void node_update(const FlowArgs<Real> &a, int x, int y)
@@ -136,19 +157,8 @@ __device__ __forceinline__ void node_update(const FlowArgs<Real> &a, int x, int 
     const size_t id = (size_t)y * a.nxp + x;
     const unsigned m = a.mask9[id];
     if (m & MASK9_SOLID) return;
-    using Off = off_t_<WIDE>;
-    constexpr Off B = sizeof(Real);
-    const Off PB = (Off)a.plane * B, o = (Off)id * B;
-    const PopBlock<Real, NT, WIDE> in(a.src, 9 * PB);
-    // all nine loads before any use (an open source reads the node's own
-    // slot, which Zou-He then replaces): no wait per direction
-    Real r[9];
-    bool open[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) r[i] = in.load(source_off<Off>(i, x, a.nx, a.nxp, m, o, PB, B, open[i]));
     Acc h[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) h[i] = open[i] ? Acc(0) : Acc(r[i]);
+    gather_node<Real, Acc, NT, WIDE>(a, x, id, m, h);
     finish_node<Real, Acc, WRITE_U, NT, WIDE>(a, x, y, id, h);
 }
 
@@ -205,6 +215,81 @@ __device__ __forceinline__ void node_update2(const FlowArgs<Real> &a, int x, int
         }
         finish_node<Real, Acc, WRITE_U, NT, WIDE>(a, x, y + k, ids[k], h);
     }
+}
+
+// Extended tile of the two-step flow launch: the shape of the ADR two-step
+// tile (64 x (EY - 2) output nodes, one block of 64 (EY + 1) threads), so
+// both launches share a grid.  FP32: 9 planes of 66 x 15 nodes, 36 KB of
+// LDS, two 16-wavefront blocks per CU at <= 64 VGPRs; FP64: EY = 10.
+template <typename Real>
+struct FlowPairTile {
+    static constexpr int EY = sizeof(Real) == 4 ? 15 : 10;
+    static constexpr int OCC = sizeof(Real) == 4 ? 8 : 6;
+    static constexpr int EX = 66, EP = EX * EY, TX = 64, TY = EY - 2;
+};
+
+// Two flow steps per launch (temporal blocking).  Step 1 updates every node
+// of the extended tile (the output nodes and a ring of one node, corners
+// included, which the diagonal populations reach) from the lattice in HBM
+// and keeps the result in LDS, rounded to Real as a store would round it;
+// step 2 gathers the output nodes from LDS, applies the same boundary rules
+// and collision, and stores them (and their velocity with WRITE_U).  Sources
+// a step-2 gather can reach are all in the tile: x +- 1 and y +- 1 of an
+// output node; sources outside the lattice are never read (open columns are
+// filled by Zou-He, rows outside the channel are walls).  Wavefront w < EY
+// takes the 64 core nodes of extended row w in step 1 and output row w in
+// step 2 (w < EY - 2); wavefront EY the two ring columns.
+template <typename Real, typename Acc, bool WRITE_U, bool NT, bool WIDE>
+__device__ __forceinline__ void pair_update(const FlowArgs<Real> &a, int bx, int by)
+{
+    using T = FlowPairTile<Real>;
+    constexpr int EY = T::EY, EX = T::EX, EP = T::EP, TY = T::TY;
+    __shared__ Real lds[9 * EP];
+    __shared__ uint16_t lmask[EP];
+    const int w = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
+    {
+        const int ey = w < EY ? w : lane >> 1;
+        const int ex = w < EY ? lane + 1 : ((lane & 1) ? EX - 1 : 0);
+        const int x = bx * 64 - 1 + ex, y = by * TY - 1 + ey;
+        if (ey < EY && x >= 0 && x < a.nx && y >= 0 && y < a.ny) {
+            const int e = ey * EX + ex;
+            const size_t id = (size_t)y * a.nxp + x;
+            const unsigned m = a.mask9[id];
+            lmask[e] = (uint16_t)m;
+            if (!(m & MASK9_SOLID)) {
+                Acc h[9];
+                gather_node<Real, Acc, false, WIDE>(a, x, id, m, h);
+                zou_he(a, x, y, h);
+                Acc u, v;
+                collide(h, Acc(a.omega), u, v);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) lds[i * EP + e] = Real(h[i]);
+            }
+        }
+    }
+    __syncthreads();
+    if (w >= TY) return;
+    const int x = bx * 64 + lane, y = by * TY + w;
+    if (x >= a.nx || y >= a.ny) return;
+    const int e = (w + 1) * EX + lane + 1;
+    const unsigned m = lmask[e];
+    if (m & MASK9_SOLID) return;
+    Real r[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int sx = x - CX[i];
+        const bool open = sx < 0 || sx >= a.nx;
+        const bool wall = i != 0 && ((m >> (OPP[i] - 1)) & 1u);
+        const int src = open ? i * EP + e : (wall ? OPP[i] * EP + e : i * EP + e - (CX[i] + CY[i] * EX));
+        r[i] = lds[src];
+    }
+    Acc h[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int sx = x - CX[i];
+        h[i] = (sx < 0 || sx >= a.nx) ? Acc(0) : Acc(r[i]);
+    }
+    finish_node<Real, Acc, WRITE_U, NT, WIDE>(a, x, y, (size_t)y * a.nxp + x, h);
 }
 
 }  // namespace flow

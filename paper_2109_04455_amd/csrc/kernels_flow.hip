@@ -40,6 +40,37 @@ __global__ __launch_bounds__(1024) void k_flow_step2r(FlowArgs<Real> a)
     flow::node_update2<Real, Acc, WRITE_U, NT, WIDE>(a, x, y);
 }
 
+// Two steps per launch (FP64 arithmetic), one block per tile of the
+// two-step tiling (flow::pair_update).
+template <typename Real, bool WRITE_U, bool NT, bool WIDE>
+__global__ __launch_bounds__(64 * (FlowPairTile<Real>::EY + 1))
+__attribute__((amdgpu_waves_per_eu(FlowPairTile<Real>::OCC))) void k_flow_pair(FlowArgs<Real> a)
+{
+    int bx, by;
+    tile_of_block(a.L, bx, by);
+    flow::pair_update<Real, double, WRITE_U, NT, WIDE>(a, bx, by);
+}
+
+template <typename Real>
+hipError_t flow_pair_launch(bool write_u, const FlowArgs<Real> &a, hipStream_t s)
+{
+    using T = FlowPairTile<Real>;
+    if (a.L.tx != T::TX || a.L.ty != T::TY || a.L.fp32_math) return hipErrorInvalidValue;
+    const dim3 g = a.L.grid(), b(64 * (T::EY + 1));
+    const int sel = (write_u ? 1 : 0) | (a.L.nontemporal ? 2 : 0) | (a.L.wide ? 4 : 0);
+    switch (sel) {
+    case 0: hipLaunchKernelGGL((k_flow_pair<Real, false, false, false>), g, b, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_flow_pair<Real, true, false, false>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_flow_pair<Real, false, true, false>), g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_flow_pair<Real, true, true, false>), g, b, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_flow_pair<Real, false, false, true>), g, b, 0, s, a); break;
+    case 5: hipLaunchKernelGGL((k_flow_pair<Real, true, false, true>), g, b, 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_flow_pair<Real, false, true, true>), g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_flow_pair<Real, true, true, true>), g, b, 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
 // Lattices below this many nodes (launch-bound: a few blocks per step) keep
 // one row per thread.
 constexpr long FLOW_TWO_ROWS_MIN_NODES = 1L << 18;
@@ -186,6 +217,12 @@ hipError_t launch_flow_step(int real_bytes, bool write_u, const FlowArgs<float> 
     else
         flow_launch(write_u, ad, s);
     return hipGetLastError();
+}
+
+hipError_t launch_flow_pair(int real_bytes, bool write_u, const FlowArgs<float> &af,
+                            const FlowArgs<double> &ad, hipStream_t s)
+{
+    return real_bytes == 4 ? flow_pair_launch(write_u, af, s) : flow_pair_launch(write_u, ad, s);
 }
 
 hipError_t launch_du_max(int real_bytes, const void *u, void *uprev, const uint16_t *mask9,

@@ -156,6 +156,50 @@ def test_c2_quarter_fp32_parity_ragged_tiles():
     _compare(g, o, w, 1e-4, 1e-4, 1e-5)
 
 
+# ------------------------------------------------------ two-step flow
+def test_flow_two_step_fp64_parity():
+    # lattices of at least 2^18 nodes (C2q: 1024 x 256) run the flow two
+    # steps per launch; 501 steps end in a single step
+    w = make_workload("C2q", real="f64")
+    ux, uy, _, _ = R.flow_steady(w.node_type, w.tau_f, w.u0, 501, tol=0)
+    c = _ctx(w, "f64")
+    c.flow_init()
+    c.flow_run(501)
+    gx, gy = c.get_velocity()
+    du = max(np.abs(gx.cpu().numpy() - ux).max(), np.abs(gy.cpu().numpy() - uy).max()) / w.u0
+    print("two-step flow, FP64, max |u - oracle| / u0", du, flush=True)
+    assert du <= 1e-10
+    c.close()
+
+
+@pytest.mark.parametrize("real", ["f32", "f64"])
+def test_flow_two_step_launches_equal_single_steps(real):
+    # flags bit 8 runs the flow one step per launch.  The two-step launch
+    # runs the same node code and rounds its intermediate state to the
+    # storage type as a store would, so the velocities agree bit for bit,
+    # after an odd step count (ending in a single step) and at the end of a
+    # steady-state run checked every 999 steps, which stops both at the same
+    # step with the same residual.  (C2q's flow settles slowly, ~2e-3 u0 per
+    # 999 steps after 120k steps: a loose tolerance, met after ~20 checks,
+    # exercises the stop.)
+    w = make_workload("C2q", real=real)
+    out = []
+    for flags in (0, 256):
+        c = _ctx(w, real, flags=flags)
+        c.flow_init()
+        c.flow_run(1001)
+        u1 = c.get_velocity()
+        steps, res, conv = c.flow_steady(200000, 999, 3e-2)
+        u2 = c.get_velocity()
+        out.append((u1, u2, steps, res, conv))
+        c.close()
+    (a1, a2, sa, ra, ca), (b1, b2, sb, rb, cb) = out
+    print(real, "steady at", sa, sb, "residual", ra / w.u0, rb / w.u0, flush=True)
+    assert ca and cb and sa == sb and ra == rb and sa < 200000 and sa % 999 == 0
+    for x, y in zip(a1 + a2, b1 + b2):
+        assert torch.equal(x, y)
+
+
 @pytest.mark.parametrize("name", ["C1", "C2"])
 def test_full_size_short_run_parity(name):
     # full-size lattices in the default launch configuration, short runs
