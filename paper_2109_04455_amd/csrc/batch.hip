@@ -131,6 +131,26 @@ __global__ __launch_bounds__(256) void k_batch_flow(const Inst<Real> *__restrict
     if (x < a.nx && y < a.ny) flow::node_update2<Real, double, WRITE_U, NT, WIDE>(a, x, y);
 }
 
+// Two flow steps of every active instance per launch: one block per slot of
+// the two-step tile table (the flow's two-step tile has the ADR's shape),
+// each block the two-step flow update of the single-lattice path.
+template <typename Real, bool WRITE_U, bool NT, bool WIDE>
+__global__ __launch_bounds__(64 * (flow::FlowPairTile<Real>::EY + 1))
+__attribute__((amdgpu_waves_per_eu(flow::FlowPairTile<Real>::OCC)))
+void k_batch_flow2(const Inst<Real> *__restrict__ insts, const int4 *__restrict__ tiles,
+                   const int *__restrict__ ntiles, int parity)
+{
+    if ((int)blockIdx.x >= *ntiles) return;
+    const int4 T = uniform_tile(tiles, blockIdx.x);
+    FlowArgs<Real> a = insts[T.x].flow;
+    if (parity) {
+        const Real *tmp = a.src;
+        a.src = a.dst;
+        a.dst = const_cast<Real *>(tmp);
+    }
+    flow::pair_update<Real, double, WRITE_U, NT, WIDE>(a, T.y, T.z);
+}
+
 template <typename Real>
 __global__ void k_build_tiles(const Inst<Real> *insts, const int *active, int n, int kind,
                               int4 *tiles, int *ntiles)
@@ -253,6 +273,7 @@ struct lbf_batch_s {
     size_t off_ptiles = 0, off_nptiles = 0;  // tile table of the two-step kernel
     int max_ptiles = 0;
     bool pair = true;  // ADR steps two per launch (flags bit 8 of instance 0 clears it)
+    bool flow_pair = true;  // flow steps likewise
     size_t off_inst = 0, off_tiles = 0, off_ntiles = 0, off_active = 0, off_obs = 0, off_du = 0,
            off_uprevp = 0, total = 0;
     int max_tiles = 0;
@@ -424,10 +445,46 @@ hipError_t enqueue_batch_pair(lbf_batch b, int parity, hipStream_t s)
 
 hipError_t enqueue_batch_step(lbf_batch b, int kind, int parity, bool write_u, hipStream_t s);
 
+template <typename Real, bool NT, bool WIDE>
+void batch_flow_pair_launch(lbf_batch b, int parity, bool write_u, hipStream_t s)
+{
+    const int4 *tiles = (const int4 *)(b->ws + b->off_ptiles);
+    const int *nt = (const int *)(b->ws + b->off_nptiles);
+    auto I = (const Inst<Real> *)(b->ws + b->off_inst);
+    const dim3 g(b->max_ptiles), blk(64 * (flow::FlowPairTile<Real>::EY + 1));
+    if (write_u)
+        hipLaunchKernelGGL((k_batch_flow2<Real, true, NT, WIDE>), g, blk, 0, s, I, tiles, nt, parity);
+    else
+        hipLaunchKernelGGL((k_batch_flow2<Real, false, NT, WIDE>), g, blk, 0, s, I, tiles, nt, parity);
+}
+
+// Two flow steps of every active instance in one launch.
+hipError_t enqueue_batch_flow_pair(lbf_batch b, int parity, bool write_u, hipStream_t s)
+{
+    const int sel = (b->nontemporal ? 1 : 0) | (b->wide ? 2 : 0);
+    auto launch = [&](auto real) {
+        using Real = decltype(real);
+        switch (sel) {
+        case 0: batch_flow_pair_launch<Real, false, false>(b, parity, write_u, s); break;
+        case 1: batch_flow_pair_launch<Real, true, false>(b, parity, write_u, s); break;
+        case 2: batch_flow_pair_launch<Real, false, true>(b, parity, write_u, s); break;
+        default: batch_flow_pair_launch<Real, true, true>(b, parity, write_u, s); break;
+        }
+    };
+    if (b->p[0].real_bytes == 4)
+        launch(float(0));
+    else
+        launch(double(0));
+    return hipGetLastError();
+}
+
 // ADR blocks run like the single-lattice path: floor((n - 1) / 2) two-step
 // launches, then single steps (the last step of a block is a single one).
+// Flow blocks: floor(n / 2) two-step launches, the last of them writing the
+// velocity, and a single step for an odd n.
 long batch_pairs(const lbf_batch_s *b, int kind, long n)
 {
+    if (kind == KIND_FLOW) return b->flow_pair ? n / 2 : 0;
     return kind == KIND_ADR && b->pair && n >= 3 ? (n - 1) / 2 : 0;
 }
 
@@ -435,7 +492,9 @@ hipError_t enqueue_batch_block(lbf_batch b, int kind, int &par, long n, hipStrea
 {
     const long pairs = batch_pairs(b, kind, n);
     hipError_t e = hipSuccess;
-    for (long i = 0; i < pairs && e == hipSuccess; ++i, par ^= 1) e = enqueue_batch_pair(b, par, s);
+    for (long i = 0; i < pairs && e == hipSuccess; ++i, par ^= 1)
+        e = kind == KIND_FLOW ? enqueue_batch_flow_pair(b, par, 2 * (i + 1) == n, s)
+                              : enqueue_batch_pair(b, par, s);
     for (long i = 2 * pairs; i < n && e == hipSuccess; ++i, par ^= 1)
         e = enqueue_batch_step(b, kind, par, i == n - 1, s);
     return e;
@@ -582,6 +641,9 @@ lbf_status lbf_batch_create(int n, const lbf_params *params, lbf_batch *out)
         ptiles += ((params[i].nx + ptx - 1) / ptx) * ((params[i].ny + pty - 1) / pty);
     b->max_ptiles = ptiles;
     b->pair = !(p0.flags & 256);
+    b->flow_pair = !(p0.flags & 256) && ptx == 64 &&
+                   pty == (p0.real_bytes == 4 ? flow::FlowPairTile<float>::TY
+                                              : flow::FlowPairTile<double>::TY);
     const size_t inst_bytes = p0.real_bytes == 4 ? sizeof(Inst<float>) : sizeof(Inst<double>);
     b->off_inst = take((size_t)n * inst_bytes);
     b->off_tiles = take((size_t)tiles * sizeof(int4));
