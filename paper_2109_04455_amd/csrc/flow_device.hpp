@@ -254,11 +254,36 @@ __device__ __forceinline__ void pair_update(const FlowArgs<Real> &a, int bx, int
         if (ey < EY && x >= 0 && x < a.nx && y >= 0 && y < a.ny) {
             const int e = ey * EX + ex;
             const size_t id = (size_t)y * a.nxp + x;
+            // the loads go out with the mask: every population from its
+            // streaming source (the node's own slot where that lies outside
+            // the lattice), bounce-back populations reloaded only next to a
+            // wall
+            using Off = off_t_<WIDE>;
+            constexpr Off B = sizeof(Real);
+            const Off PB = (Off)a.plane * B, o = (Off)id * B;
+            const PopBlock<Real, false, WIDE> in(a.src, 9 * PB);
             const unsigned m = a.mask9[id];
+            Real r[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const int sx = x - CX[i], sy = y - CY[i];
+                const bool inside = sx >= 0 && sx < a.nx && sy >= 0 && sy < a.ny;
+                const Off back = (Off)(ptrdiff_t)(CX[i] + CY[i] * a.nxp) * B;  // modular
+                r[i] = in.load(inside ? o + i * PB - back : o + i * PB);
+            }
             lmask[e] = (uint16_t)m;
             if (!(m & MASK9_SOLID)) {
+                if (m & 0xFFu) {
+#pragma unroll
+                    for (int i = 1; i < 9; ++i)
+                        if ((m >> (OPP[i] - 1)) & 1u) r[i] = in.load(o + OPP[i] * PB);
+                }
                 Acc h[9];
-                gather_node<Real, Acc, false, WIDE>(a, x, id, m, h);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    const int sx = x - CX[i];
+                    h[i] = (sx < 0 || sx >= a.nx) ? Acc(0) : Acc(r[i]);
+                }
                 zou_he(a, x, y, h);
                 Acc u, v;
                 collide(h, Acc(a.omega), u, v);
